@@ -1,0 +1,159 @@
+"""Benchmark: decoded frames/s of the two-stage MP-WSD decoder on one GPU.
+
+One step = the whole decoder over one batch resident in HBM: int8 LLR
+quantization, stage-1 SC-list decoding with the CRC test, compaction of the
+failing frames, T iterations of the stage-2 move search / apply, and the
+final choice.  Workload: RM(3,7) (N=128, K=64 = 58 payload + CRC-6), BPSK
+over AWGN at Eb/N0 = 2.5 dB, 65536 frames, int8 LLRs (scale 8/sigma^2),
+L = 8 anchors, T = 8 iterations, 94488 moves (seeded synthetic data).
+
+Prints one JSON line.  The roofline entry is for the stage-2 move-search
+kernel: dense int8 MFMA work 2 P N per searched path and iteration, over
+that kernel's launch durations measured with HIP events on the stream it
+runs on.  The CPU baseline is the test oracle on a bounded sample of the
+same frames.
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MI355X_INT8_DENSE_TOPS = 5000.0  # AMD published dense int8 MFMA peak (TOP/s)
+MI355X_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=65536)
+    ap.add_argument("--ebn0", type=float, default=2.5)
+    ap.add_argument("--L", type=int, default=8)
+    ap.add_argument("--T", type=int, default=8)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-frames", type=int, default=8192, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, y, L, T, nframes, threads):
+    import oracle
+    from paper_2602_08501_amd import synth  # noqa: F401
+    q = oracle.quantize(y[:nframes], wl.llr_scale).astype(np.float64)
+    oracle.moves(wl.r, wl.m)  # table built outside the timed region
+    t0 = time.perf_counter()
+    oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": nframes / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d frames of the same batch (int8 LLRs, full two-stage decode), %.1f s wall"
+                      % (nframes, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus %d requested); "
+              "the decoder shards by frame with no communication, see DESIGN.md" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2602_08501_amd import decoder as D
+    from paper_2602_08501_amd import synth
+
+    wl = dataclasses.replace(synth.RM37, ebn0_db=args.ebn0)
+    F, L, T = args.frames, args.L, args.T
+    dev = "cuda:0"
+    pay, c_tx, y = synth.generate(wl, args.seed, 0, F)
+    code = D.Code(wl.r, wl.m, dev)
+    y_d = torch.from_numpy(y).to(dev)
+    q_d = torch.empty(y.shape, dtype=torch.int8, device=dev)
+    s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
+          "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)}
+    st = D.Stage2([(code, F)], L, T, "i8", dev, want_moves=False)
+    stream = torch.cuda.Stream()
+    scale = float(wl.llr_scale)
+    from paper_2602_08501_amd import _lib
+
+    def step(events=None):
+        _lib.check(_lib.mpwsd_quantize_llr(y_d.data_ptr(), y_d.numel(), scale, q_d.data_ptr(), None,
+                                           stream.cuda_stream))
+        D.stage1(code, L, q_d, wl.crc_len, wl.crc_poly, out=s1, stream=stream)
+        st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream, events=events)
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+    torch.cuda.synchronize()
+
+    # per-step search-kernel events (created by a first record on the stream)
+    evs = []
+    for _ in range(args.steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T)]
+        for x in e:
+            x.record(stream)
+        evs.append(e)
+    torch.cuda.synchronize()
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t_start.elapsed_time(t_end) / args.steps
+    stats = st.stats.cpu().numpy()
+    cols = stats[1:1 + T].astype(np.int64)
+    dense_ops = 2.0 * code.P * code.N * cols  # per launch
+    search_ms = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
+                          for k in range(args.steps)])
+    launches = search_ms.mean(0)
+    achieved = float(dense_ops.sum() / (launches.sum() * 1e-3) / 1e12)
+    out = st.outs[0]
+    cw = np.unpackbits(out["cw"].cpu().numpy(), axis=-1, bitorder="little")
+    fer = float((cw != c_tx).any(1).mean())
+    f2 = int(stats[0])
+    moves_evals = float(code.P * cols.sum())
+    res = {
+        "metric": "decoded frames/sec at FER parity; stage-2 move-evals/sec (% int8 MFMA peak)",
+        "value": F / (ms * 1e-3),
+        "unit": "decoded frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic (seeded BPSK/AWGN frames, random payloads)",
+        "config": {"workload": "RM(3,7) N=128 K=64 (58+CRC-6), Eb/N0 %.2f dB, %d frames, int8 LLRs, "
+                               "SCL L=%d, T=%d, %d moves" % (args.ebn0, F, L, T, code.P),
+                   "frames": F, "stage2_frames": f2, "p_act": f2 / F,
+                   "paths_searched_per_iteration": cols.tolist(), "fer": fer},
+        "stage2_move_evals_per_s": moves_evals / (launches.sum() * 1e-3),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_INT8_DENSE_TOPS, "unit": "TOP/s",
+                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": None,
+                     "kernel": "search_i8_kernel",
+                     "launch_ms": launches.tolist(),
+                     "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)"},
+        "wall_s": wall,
+    }
+    if args.cpu_frames > 0:
+        thr = args.cpu_threads or min(16, os.cpu_count() or 1)
+        res["cpu_baseline"] = cpu_baseline(wl, y, L, T, min(args.cpu_frames, F), thr)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * mpwsd.h - multipoint code-weight sphere decoding (MP-WSD) on AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The decoder of Jo, Choi, Kim and Lee, "Multipoint Code-Weight Sphere
+ * Decoding: Parallel Near-ML Decoding for Short-Blocklength Codes", for
+ * Reed-Muller codes RM(r, m) with 5 <= m <= 8 (N = 2^m = 32 ... 256):
+ *   stage 1 (Sec. III-A): successive-cancellation list decoding with a CRC;
+ *   stage 2 (Sec. III-B, Alg. 1): for frames whose stage-1 CRC fails, L
+ *     parallel greedy searches over the precomputed sphere S_1(0) (Eq. (3)),
+ *     each scoring every move by its correlation gain (Eq. (5)), followed by
+ *     the choice of the best path.
+ *
+ * Conventions shared by every call
+ *   - Bit vectors are packed least-significant-bit first: bit j of a vector
+ *     of N bits is bit (j % 8) of byte j / 8; a vector occupies N/8 bytes.
+ *   - Code RM(r, m) in Kronecker form: u in {0,1}^N, c = u F^{(x)m},
+ *     F = [[1,0],[1,1]], natural index order.  Information positions are
+ *     A = { i : popcount(i) >= m - r } in ascending order; information bit t
+ *     of v = payload || crc is u_{A[t]}.
+ *   - CRC (Sec. II-B, K' = K + K_crc): remainder of p(x) x^crc_len modulo
+ *     g(x) (crc_poly includes the x^crc_len term; 0x43 is x^6 + x + 1),
+ *     first bit = highest degree, no reflection, zero init, no final xor.
+ *   - LLR inputs are either int8 q (dtype MPWSD_I8) or float y (MPWSD_F32),
+ *     row-major [F][N].  A positive value favours bit 0 (x = 1 - 2c).
+ *   - Device pointers are plain device addresses (hipMalloc or a framework
+ *     tensor); the caller owns every buffer.  The library allocates no device
+ *     memory and keeps no mutable global state; all work is enqueued on the
+ *     caller's stream and nothing synchronises it.
+ *   - Every call returns MPWSD_OK (0) or a negative error code; arguments are
+ *     validated before anything is enqueued, and on error nothing is written.
+ *     mpwsd_last_error() describes the last failure of the calling thread.
+ *     Faults of enqueued kernels surface at the caller's stream sync.
+ */
+#ifndef MPWSD_H
+#define MPWSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MPWSD_OK = 0,
+    MPWSD_ERR_ARG = -1,         /* null pointer, negative size, bad enum */
+    MPWSD_ERR_SIZE = -2,        /* caller buffer or workspace too small */
+    MPWSD_ERR_DEVICE = -3,      /* a HIP call failed while enqueueing */
+    MPWSD_ERR_UNSUPPORTED = -4  /* parameters outside the supported range */
+};
+
+enum { MPWSD_I8 = 0, MPWSD_F32 = 1 };
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* mpwsd_last_error(void);
+
+/*
+ * mpwsd_build_moves - the code-weight sphere S_1(0) without the zero word
+ * (Sec. II-C, Eq. (2)-(3); precomputed once, Sec. III-B).
+ *
+ * For RM(r, m) with 1 <= r < m <= 8 these are the P minimum-weight
+ * codewords, of weight w = 2^(m-r): the incidence vectors of the
+ * (m-r)-dimensional flats of EG(m, 2), coordinate j being the point whose
+ * bits are the bits of j.  They are written in canonical order: ascending
+ * by the sorted support (j_1 < ... < j_w) compared lexicographically; a
+ * move index anywhere in this API is a row of this table.
+ *
+ * moves: HOST buffer of cap_bytes bytes receiving P rows of N/8 bytes, or
+ *        NULL to query the sizes only.
+ * P, N, w: out (any may be NULL).
+ * Errors: MPWSD_ERR_UNSUPPORTED for r, m out of range; MPWSD_ERR_SIZE when
+ * moves != NULL and cap_bytes < P * N / 8 (sizes are still reported).
+ * Host-only, thread-safe.
+ */
+int mpwsd_build_moves(int r, int m, uint8_t* moves, size_t cap_bytes,
+                      int64_t* P, int* N, int* w);
+
+/*
+ * mpwsd_quantize_llr - int8 LLR quantizer (device):
+ *   q[i] = clamp(round_half_even(fl32(y[i] * scale)), -127, 127)
+ * with scale typically 8 / sigma^2 (four times the LLR 2y/sigma^2).
+ * Non-finite y[i] gives q[i] = 0 and bumps *bad (if bad != NULL; device
+ * int32, not cleared by this call).
+ * y: device float[n]; q: device int8[n].
+ */
+int mpwsd_quantize_llr(const float* y, int64_t n, float scale, int8_t* q,
+                       int32_t* bad, hipStream_t stream);
+
+/*
+ * mpwsd_stage1_scl - stage 1, Sec. III-A: min-sum successive-cancellation
+ * list decoding with list size L on RM(r, m), then the CRC test of the most
+ * reliable candidate.
+ *
+ * Decoder: f(a,b) = sgn(a) sgn(b) min(|a|,|b|) with sgn(0) = +1,
+ * g(a,b,v) = b + (1-2v) a, hard decision HD(l) = 1 iff l < 0, path metric
+ * PM += |l| when the bit taken differs from HD(l), frozen bits are 0.  At
+ * an information bit the 2n children are ranked by (PM, parent slot, bit)
+ * and the first min(L, 2n) survive in that order.  Integer LLRs are decoded
+ * in exact int32 arithmetic, float LLRs in IEEE binary32 without
+ * contraction.
+ *
+ * llr: device [F][N], int8 (MPWSD_I8) or float (MPWSD_F32).
+ * anchors: device out [F][L][N/8]: the list in ascending (PM, slot) order,
+ *          the initial list of Sec. III-B.
+ * crc_ok: device out [F]: 1 iff the first list entry's information bits
+ *         pass the CRC (the frame is decided by stage 1); 0 otherwise, and
+ *         always 0 when crc_len == 0 (no CRC: every frame goes on).
+ * pm: device out [F][L] path metrics (int32 or float bits), may be NULL.
+ * Supported: 5 <= m <= 8, 1 <= r < m, L in {1,2,4,8,16,32} with L <= 2^K,
+ * 0 <= crc_len <= min(16, K).
+ */
+int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L,
+                     const void* llr, int dtype, int64_t F,
+                     uint8_t* anchors, uint8_t* crc_ok, int32_t* pm,
+                     hipStream_t stream);
+
+/*
+ * One group of frames of one code for stage 2.
+ */
+typedef struct mpwsd_segment {
+    int r, m;                  /* code RM(r, m) */
+    const uint8_t* moves;      /* device [P][N/8], the table of mpwsd_build_moves */
+    int64_t P;                 /* number of moves */
+    const void* llr;           /* device [F][N]: int8 q or float y */
+    int dtype;                 /* MPWSD_I8 or MPWSD_F32 */
+    int64_t F;                 /* frames */
+    const uint8_t* anchors;    /* device [F][L][N/8], list of stage 1 */
+    const uint8_t* crc_ok;     /* device [F]; 1 = decided by stage 1.  NULL:
+                                  every frame goes to stage 2 (always-on) */
+    uint8_t* out_cw;           /* device out [F][N/8]: decision for every frame */
+    int32_t* out_k;            /* device out [F]: chosen path (0 when stage 1
+                                  decided); may be NULL */
+    int32_t* out_metric;       /* device out [F]: metric of the decision (int8:
+                                  M(c) = sum_{c_j=1} q_j; float: the bits of
+                                  ||y - x(c)||^2 in binary32); may be NULL */
+    int32_t* out_moves;        /* device out [F][L][T]: accepted move index per
+                                  path and iteration, -1 = none; may be NULL */
+} mpwsd_segment;
+
+/*
+ * mpwsd_workspace_bytes - device workspace needed by mpwsd_decode_batch for
+ * these segments, L and T (0 on invalid arguments; see mpwsd_last_error).
+ */
+size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T);
+
+/*
+ * mpwsd_decode_batch - stage 2, Sec. III-B, Eq. (4)-(5), Alg. 1.
+ *
+ * Frames with crc_ok = 1 take their first anchor as the decision.  The
+ * others are compacted on the device into one list, and each of their L
+ * anchors starts a path.  In each of T iterations every active path with
+ * centre c scores all P moves w_p by
+ *     S_p = sum_{j in supp(w_p)} z_j,   z_j = llr_j (1 - 2 c_j)
+ * (the squared distance changes by 4 S_p; S_p = -G(w_p)/2 of Eq. (5)),
+ * takes the smallest p attaining min_p S_p, and moves to c xor w_p iff
+ * S_p < 0; otherwise the path stops (a stopped path could never move
+ * again).  The decision is the path with the smallest metric, ties to the
+ * smallest path index.  In int8 mode all sums are exact integers; in float
+ * mode S_p is summed in binary32 in ascending j and the final metric is
+ * ||y - x(c)||^2 summed in binary32 in ascending j.
+ *
+ * segs[nseg]: host array.  All segments must use the same dtype.
+ * ws: device workspace of ws_bytes >= mpwsd_workspace_bytes(...) bytes.
+ * stats: device out int32[2 + T] or NULL: [0] = frames sent to stage 2
+ *        (summed over segments), [1 + t] = paths searched in iteration t,
+ *        [1 + T] = internal consistency failures (0 expected).
+ * Supported: 5 <= m <= 8, 1 <= r < m, 1 <= L <= 32, 1 <= T <= 64.
+ */
+int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, int T,
+                       void* ws, size_t ws_bytes, int32_t* stats,
+                       hipStream_t stream);
+
+/*
+ * mpwsd_decode_batch_timed - mpwsd_decode_batch that also records, on the
+ * same stream, events[2 (s T + t)] right before and events[2 (s T + t) + 1]
+ * right after the move-search kernel of iteration t of segment s, so the
+ * caller can time the search with hipEventElapsedTime after its own sync.
+ * events: host array of nseg * 2 * T events created by the caller.  Nothing
+ * else differs; in particular nothing is synchronised.
+ */
+int mpwsd_decode_batch_timed(const mpwsd_segment* segs, int nseg, int L, int T,
+                             void* ws, size_t ws_bytes, int32_t* stats,
+                             hipEvent_t* events, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPWSD_H */

@@ -1,0 +1,118 @@
+"""ctypes binding of libmpwsd.so: the C-ABI declared in include/mpwsd.h.
+
+Argument marshalling only.  Every step of the decoder runs in the library's
+HIP kernels; there is no fallback: if the library is missing this module
+raises on first use.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpwsd.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpwsd.h")
+
+MPWSD_OK, MPWSD_ERR_ARG, MPWSD_ERR_SIZE, MPWSD_ERR_DEVICE, MPWSD_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+MPWSD_I8, MPWSD_F32 = 0, 1
+
+_p, _i, _i64, _u32, _f, _sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32,
+                               ctypes.c_float, ctypes.c_size_t)
+
+
+class Segment(ctypes.Structure):
+    """struct mpwsd_segment."""
+    _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("llr", _p), ("dtype", _i),
+                ("F", _i64), ("anchors", _p), ("crc_ok", _p), ("out_cw", _p), ("out_k", _p),
+                ("out_metric", _p), ("out_moves", _p)]
+
+
+class MpwsdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (code %d)" % (msg, code))
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmpwsd.so is not built (run __graft_entry__.build() or "
+                              "python paper_2602_08501_amd/build.py): " + LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.mpwsd_last_error.restype = ctypes.c_char_p
+        lib.mpwsd_last_error.argtypes = []
+        lib.mpwsd_build_moves.argtypes = [_i, _i, _p, _sz, _p, _p, _p]
+        lib.mpwsd_quantize_llr.argtypes = [_p, _i64, _f, _p, _p, _p]
+        lib.mpwsd_stage1_scl.argtypes = [_i, _i, _i, _u32, _i, _p, _i, _i64, _p, _p, _p, _p]
+        lib.mpwsd_workspace_bytes.argtypes = [ctypes.POINTER(Segment), _i, _i, _i]
+        lib.mpwsd_workspace_bytes.restype = _sz
+        lib.mpwsd_decode_batch.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p, _p]
+        lib.mpwsd_decode_batch_timed.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p,
+                                                 ctypes.POINTER(_p), _p]
+        for name in ("mpwsd_build_moves", "mpwsd_quantize_llr", "mpwsd_stage1_scl", "mpwsd_decode_batch",
+                     "mpwsd_decode_batch_timed"):
+            getattr(lib, name).restype = _i
+        _lib = lib
+    return _lib
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/mpwsd.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(mpwsd_\w+)\s*\(", text, re.M)))
+
+
+def last_error() -> str:
+    return load().mpwsd_last_error().decode()
+
+
+def check(rc: int) -> int:
+    if rc != MPWSD_OK:
+        raise MpwsdError(rc, last_error())
+    return rc
+
+
+# ------------------------------------------------------------------ the C calls
+def mpwsd_build_moves(r: int, m: int, moves_ptr, cap_bytes: int):
+    """Returns (rc, P, N, w); moves_ptr may be None for a size query."""
+    P, N, w = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+    rc = load().mpwsd_build_moves(r, m, moves_ptr, cap_bytes, ctypes.byref(P), ctypes.byref(N),
+                                  ctypes.byref(w))
+    return rc, P.value, N.value, w.value
+
+
+def mpwsd_quantize_llr(y_ptr, n: int, scale: float, q_ptr, bad_ptr, stream: int) -> int:
+    return load().mpwsd_quantize_llr(y_ptr, n, scale, q_ptr, bad_ptr, stream)
+
+
+def mpwsd_stage1_scl(r, m, crc_len, crc_poly, L, llr_ptr, dtype, F, anchors_ptr, crc_ok_ptr,
+                     pm_ptr, stream) -> int:
+    return load().mpwsd_stage1_scl(r, m, crc_len, crc_poly, L, llr_ptr, dtype, F, anchors_ptr,
+                                   crc_ok_ptr, pm_ptr, stream)
+
+
+def segments_array(segs):
+    arr = (Segment * len(segs))(*segs)
+    return arr
+
+
+def mpwsd_workspace_bytes(segs, L: int, T: int) -> int:
+    arr = segments_array(segs)
+    return load().mpwsd_workspace_bytes(arr, len(segs), L, T)
+
+
+def mpwsd_decode_batch(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, stream) -> int:
+    arr = segments_array(segs)
+    return load().mpwsd_decode_batch(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, stream)
+
+
+def mpwsd_decode_batch_timed(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, event_handles,
+                             stream) -> int:
+    arr = segments_array(segs)
+    evs = (_p * len(event_handles))(*event_handles)
+    return load().mpwsd_decode_batch_timed(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, evs, stream)

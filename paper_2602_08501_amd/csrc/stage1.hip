@@ -1,0 +1,312 @@
+// Stage 1 (Sec. III-A): LLR quantizer and min-sum successive-cancellation
+// list decoding with a CRC on the most reliable candidate.
+//
+// Mapping on CDNA4: one lane per list path and L consecutive lanes per frame,
+// so a 64-wide wavefront decodes 64/L frames in lock step; all lanes of a
+// wave visit the same leaf at the same time, which keeps control flow
+// uniform.  Each path owns one LLR buffer per tree level in LDS (level l has
+// 2^l values, stored element-major so that the 64 lanes of a wave hit 64
+// consecutive slots).  A path reads its parent level through a per-level
+// owner index instead of copying buffers when paths are cloned: at a given
+// leaf every path rewrites the same levels, each into its own buffer, so a
+// buffer another path still refers to is never overwritten while needed.
+// Cloning therefore copies only the owner indices, the decided bits and the
+// metric.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+
+template <bool FLOAT> struct Arith;
+template <> struct Arith<false> {
+    using V = int32_t;        // LLR arithmetic
+    using S = int16_t;        // LDS storage: |l| <= 127 * 2^(m - level) <= 32512
+    __device__ static V load_ch(const void* p, int64_t i) { return (V)((const int8_t*)p)[i]; }
+    __device__ static uint32_t key_bits(V pm) { return (uint32_t)pm; }
+};
+template <> struct Arith<true> {
+    using V = float;
+    using S = float;
+    __device__ static V load_ch(const void* p, int64_t i) { return ((const float*)p)[i]; }
+    __device__ static uint32_t key_bits(V pm) { return __float_as_uint(pm); }
+};
+
+template <typename V> __device__ inline V f_minsum(V a, V b)
+{
+    V ma = a < 0 ? -a : a, mb = b < 0 ? -b : b;
+    V m = ma < mb ? ma : mb;
+    return ((a < 0) != (b < 0)) ? -m : m;
+}
+
+// Polar transform x -> x F^{(x)lev} of the n = 2^lev bits held in w[]
+// (bit k of position k, 32 per word): within-word butterflies for the first
+// five factors, whole-word xors for the rest.
+template <int NW> __device__ inline void polar_bits(uint32_t (&w)[NW], int lev)
+{
+    const uint32_t MK[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu, 0x0000FFFFu};
+    const int sw = lev < 5 ? lev : 5;
+    for (int s = 0; s < sw; ++s)
+#pragma unroll
+        for (int i = 0; i < NW; ++i) w[i] ^= (w[i] >> (1 << s)) & MK[s];
+    for (int s = 5; s < lev; ++s) {
+        const int h = 1 << (s - 5);
+#pragma unroll
+        for (int i = 0; i < NW; ++i)
+            if ((i & h) == 0 && i + h < NW) w[i] ^= w[i + h];
+    }
+}
+
+template <int M, bool FLOAT>
+__global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F, int L,
+                                                   uint64_t info0, uint64_t info1, uint64_t info2, uint64_t info3,
+                                                   int crc_len, uint32_t crc_poly,
+                                                   uint8_t* __restrict__ anchors, uint8_t* __restrict__ crc_ok,
+                                                   int32_t* __restrict__ pm_out)
+{
+    using A = Arith<FLOAT>;
+    using V = typename A::V;
+    using S = typename A::S;
+    constexpr int N = 1 << M;
+    constexpr int NW = N / 32;  // words of decided bits per path
+    __shared__ S buf[(N - 1) * WAVE];
+    __shared__ uint64_t key_s[2 * WAVE];
+    __shared__ int sel_s[WAVE];
+    __shared__ V cpm_s[WAVE];
+    __shared__ uint64_t ptr_s[WAVE];
+    __shared__ uint32_t ub_s[NW * WAVE];
+    __shared__ int valid_s[WAVE];
+    __shared__ int cvalid_s[WAVE];
+
+    const int lane = threadIdx.x;
+    const int lgL = __builtin_ctz(L);
+    const int slot = lane & (L - 1);
+    const int gbase = lane - slot;  // first lane of this frame group
+    const int64_t frame = (int64_t)blockIdx.x * (WAVE >> lgL) + (lane >> lgL);
+    const bool live = frame < F;
+    const int64_t fr = live ? frame : 0;
+    const uint64_t info[4] = {info0, info1, info2, info3};
+
+    V pm = 0;
+    bool valid = (slot == 0);
+    uint64_t ptrs = 0;  // byte l: group slot owning this path's level-l buffer
+    uint32_t ub[NW];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) ub[i] = 0;
+    for (int l = 0; l < M; ++l) ptrs |= (uint64_t)slot << (8 * l);
+
+    for (int i = 0; i < N; ++i) {
+        const int d = (i == 0) ? M - 1 : __builtin_ctz(i);
+        V lam = 0;
+        for (int lev = d; lev >= 0; --lev) {
+            const int n = 1 << lev;
+            const int obase = n - 1;
+            const bool use_g = (lev == d) && (i > 0);
+            uint32_t ps[NW > 0 ? NW : 1];
+            if (use_g) {
+                // left sibling covers leaves [i - n, i): its decided bits, re-encoded
+                const int st = i - n;
+                if (n < 32) {
+                    ps[0] = (ub[st >> 5] >> (st & 31)) & ((1u << n) - 1u);
+                } else {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) ps[w] = (w < n / 32) ? ub[(st >> 5) + w] : 0u;
+                }
+                polar_bits(ps, lev);
+            }
+            if (lev + 1 == M) {
+                const int64_t cb = fr * N;
+                for (int k = 0; k < n; ++k) {
+                    V a = A::load_ch(llr, cb + k), b = A::load_ch(llr, cb + k + n);
+                    V o;
+                    if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
+                    else o = f_minsum(a, b);
+                    buf[(obase + k) * WAVE + lane] = (S)o;
+                    lam = o;
+                }
+            } else {
+                const int owner = gbase + (int)((ptrs >> (8 * (lev + 1))) & 0xFF);
+                const int pbase = 2 * n - 1;
+                for (int k = 0; k < n; ++k) {
+                    V a = (V)buf[(pbase + k) * WAVE + owner];
+                    V b = (V)buf[(pbase + k + n) * WAVE + owner];
+                    V o;
+                    if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
+                    else o = f_minsum(a, b);
+                    buf[(obase + k) * WAVE + lane] = (S)o;
+                    lam = o;
+                }
+            }
+            ptrs = (ptrs & ~(0xFFull << (8 * lev))) | ((uint64_t)slot << (8 * lev));
+            __builtin_amdgcn_wave_barrier();
+        }
+        const bool frozen = ((info[i >> 6] >> (i & 63)) & 1ull) == 0;
+        const V mag = lam < 0 ? -lam : lam;
+        const int hd = lam < 0 ? 1 : 0;
+        if (frozen) {
+            if (valid && hd) pm = pm + mag;
+            continue;  // u_i = 0 already
+        }
+        // information bit: rank the 2L children by (PM, parent slot, bit)
+        V cp[2];
+        cp[0] = (hd == 0) ? pm : (V)(pm + mag);
+        cp[1] = (hd == 1) ? pm : (V)(pm + mag);
+        uint64_t key[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint64_t hi = valid ? (uint64_t)A::key_bits(cp[u]) : 0xFFFFFFFFull;
+            key[u] = (hi << 8) | (uint64_t)(2 * slot + u);
+            key_s[2 * lane + u] = key[u];
+        }
+        ptr_s[lane] = ptrs;
+        valid_s[lane] = valid ? 1 : 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) ub_s[w * WAVE + lane] = ub[w];
+        __syncthreads();
+        int rank[2] = {0, 0};
+        for (int c = 0; c < 2 * L; ++c) {
+            const uint64_t o = key_s[2 * gbase + c];
+            rank[0] += o < key[0];
+            rank[1] += o < key[1];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (rank[u] < L) {
+                sel_s[gbase + rank[u]] = 2 * slot + u;
+                cpm_s[gbase + rank[u]] = cp[u];
+                cvalid_s[gbase + rank[u]] = valid ? 1 : 0;
+            }
+        __syncthreads();
+        const int c = sel_s[lane];
+        const int par = gbase + (c >> 1);
+        pm = cpm_s[lane];
+        valid = cvalid_s[lane] != 0;
+        ptrs = ptr_s[par];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) ub[w] = ub_s[w * WAVE + par];
+        ub[i >> 5] |= (uint32_t)(c & 1) << (i & 31);
+        __syncthreads();
+    }
+
+    // final order: (PM, slot) ascending
+    const uint64_t fkey = ((uint64_t)(valid ? A::key_bits(pm) : 0xFFFFFFFFu) << 8) | (uint64_t)slot;
+    key_s[lane] = fkey;
+    __syncthreads();
+    int rank = 0;
+    for (int c = 0; c < L; ++c) rank += key_s[gbase + c] < fkey;
+    uint32_t cw[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) cw[w] = ub[w];
+    polar_bits(cw, M);
+    if (live) {
+        uint32_t* dst = (uint32_t*)(anchors + ((size_t)frame * L + rank) * (N / 8));
+#pragma unroll
+        for (int w = 0; w < NW; ++w) dst[w] = cw[w];
+        if (pm_out) pm_out[frame * L + rank] = (int32_t)A::key_bits(pm);
+        if (rank == 0) {
+            int ok = 0;
+            if (crc_len > 0) {
+                const uint32_t top = 1u << (crc_len - 1), mask = (1u << crc_len) - 1u;
+                uint32_t reg = 0;
+                for (int j = 0; j < N; ++j) {
+                    if (((info[j >> 6] >> (j & 63)) & 1ull) == 0) continue;
+                    const uint32_t bit = (ub[j >> 5] >> (j & 31)) & 1u;
+                    const uint32_t fb = ((reg & top) ? 1u : 0u) ^ bit;
+                    reg = (reg << 1) & mask;
+                    if (fb) reg ^= crc_poly & mask;
+                }
+                ok = reg == 0;
+            }
+            crc_ok[frame] = (uint8_t)ok;
+        }
+    }
+}
+
+__global__ void quantize_kernel(const float* __restrict__ y, int64_t n, float s, int8_t* __restrict__ q,
+                                int32_t* __restrict__ bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = y[i];
+        if (!isfinite(v)) {
+            q[i] = 0;
+            if (bad) atomicAdd(bad, 1);
+            continue;
+        }
+        float t = rintf(__fmul_rn(v, s));  // a product overflowing to +-inf clamps below
+        t = fminf(fmaxf(t, -127.0f), 127.0f);
+        q[i] = (int8_t)t;
+    }
+}
+
+template <int M, bool FL>
+void launch_scl(const void* llr, int64_t F, int L, const uint64_t* info, int crc_len, uint32_t poly,
+                uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, hipStream_t s)
+{
+    const int64_t per = WAVE / L;
+    const int64_t blocks = (F + per - 1) / per;
+    hipLaunchKernelGGL((scl_kernel<M, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, L, info[0], info[1],
+                       info[2], info[3], crc_len, poly, anchors, crc_ok, pm);
+}
+
+}  // namespace
+
+extern "C" int mpwsd_quantize_llr(const float* y, int64_t n, float scale, int8_t* q, int32_t* bad,
+                                  hipStream_t stream)
+{
+    mpwsd::clear_error();
+    if (n < 0 || (n > 0 && (!y || !q))) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_quantize_llr: bad arguments");
+    if (!std::isfinite(scale)) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_quantize_llr: scale must be finite");
+    if (n == 0) return MPWSD_OK;
+    const int64_t want = (n + 255) / 256;
+    const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(quantize_kernel, dim3(blocks), dim3(256), 0, stream, y, n, scale, q, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_quantize_llr: %s", hipGetErrorString(e));
+    return MPWSD_OK;
+}
+
+extern "C" int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L, const void* llr, int dtype,
+                                int64_t F, uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, hipStream_t stream)
+{
+    using namespace mpwsd;
+    clear_error();
+    if (m < 5 || m > 8 || r < 1 || r >= m)
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: need 1 <= r < m, 5 <= m <= 8 (r=%d m=%d)", r, m);
+    const int K = rm_dimension(r, m);
+    if (L < 1 || L > 32 || (L & (L - 1)) != 0)
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: L must be a power of two <= 32 (L=%d)", L);
+    if (K < 6 && L > (1 << K))
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: L=%d exceeds the code size 2^%d", L, K);
+    if (crc_len < 0 || crc_len > 16 || crc_len > K)
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: crc_len must be in [0, min(16, K)] (got %d)", crc_len);
+    if (crc_len > 0 && ((crc_poly >> crc_len) & 1u) == 0)
+        return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: crc_poly must include the x^%d term", crc_len);
+    if (dtype != MPWSD_I8 && dtype != MPWSD_F32) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: bad dtype %d", dtype);
+    if (F < 0) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: F < 0");
+    if (F == 0) return MPWSD_OK;
+    if (!llr || !anchors || !crc_ok) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: null pointer");
+    if ((reinterpret_cast<uintptr_t>(anchors) & 3u) != 0)
+        return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: anchors must be 4-byte aligned");
+    uint64_t info[4] = {0, 0, 0, 0};
+    for (int i = 0; i < (1 << m); ++i)
+        if (__builtin_popcount((unsigned)i) >= m - r) info[i >> 6] |= 1ull << (i & 63);
+    const bool fl = dtype == MPWSD_F32;
+    switch (m) {
+    case 5: fl ? launch_scl<5, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
+               : launch_scl<5, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
+    case 6: fl ? launch_scl<6, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
+               : launch_scl<6, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
+    case 7: fl ? launch_scl<7, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
+               : launch_scl<7, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
+    default: fl ? launch_scl<8, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
+                : launch_scl<8, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MPWSD_ERR_DEVICE, "mpwsd_stage1_scl: %s", hipGetErrorString(e));
+    return MPWSD_OK;
+}

@@ -1,0 +1,732 @@
+// Stage 2 (Sec. III-B, Eq. (4)-(5), Alg. 1): multipoint code-weight sphere
+// decoding of the frames whose stage-1 CRC failed.
+//
+// A "column" is one (failing frame, path) pair.  Per column the workspace
+// holds the centre c (packed bits), z = llr * (1 - 2c) and the metric.  The
+// move search of one iteration is the contraction S = W Z of the move matrix
+// W (P x N, 0/1) with the z columns, followed by an argmin over P:
+//   * int8 form: W is kept bit-packed in HBM; each workgroup unpacks a chunk
+//     of 128 moves into LDS once and all its waves feed it to
+//     v_mfma_i32_16x16x64_i8 against z fragments that stay in VGPRs for the
+//     whole sweep.  The epilogue keeps a running minimum with v_min3 and, per
+//     128-move chunk, folds (minimum << 16 | chunk) into one int32 key, so
+//     the first chunk holding the column minimum survives; the exact move is
+//     recovered afterwards by rescoring that single chunk.
+//   * float form: the same contraction summed sequentially in binary32 in
+//     ascending position order on the vector ALUs, with the exact move index
+//     carried in a 64-bit key.
+// Work is split over (column tile x move chunk) units spread evenly over a
+// fixed, device-filling grid; split results meet in an atomicMin per column,
+// which is order independent, so the result does not depend on the split.
+// After each search a resolve pass applies the moves, logs them and
+// compacts the columns that moved into the next iteration's active list
+// (a column that did not move can never move again).  All counts live in
+// device memory, so T iterations enqueue without any host round trip and
+// can be captured in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int RC = 128;  // moves per chunk
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- workspace
+struct SegWs {
+    int32_t* hdr;     // [0]=F2 [1]=err [2..2+T] active count per iteration
+    int32_t* fid;     // [F] compacted failing frames
+    int32_t* slot;    // [F] frame -> compacted slot (-1 when decided)
+    int32_t* act[2];  // [F*L] active column lists (ping-pong)
+    int32_t* key32;   // [F*L] int8 form: (S << 16 | chunk) minima
+    uint64_t* key64;  // [F*L] float form: (orderable S << 32 | p) minima
+    int32_t* metric;  // [F*L] int8: M; float: unused
+    uint8_t* cw;      // [F*L][N/8] centres
+    void* z;          // [F*L][KP] int8 or [F*L][N] float
+    size_t bytes;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+int kpad(int N) { return N < 64 ? 64 : N; }
+
+SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
+{
+    const size_t F = (size_t)sg.F, C = F * (size_t)L;
+    const int N = 1 << sg.m;
+    SegWs w{};
+    size_t off = 0;
+    auto take = [&](size_t b) { uint8_t* p = base ? base + off : nullptr; off += align_up(b); return p; };
+    w.hdr = (int32_t*)take(sizeof(int32_t) * (size_t)(4 + T));
+    w.fid = (int32_t*)take(sizeof(int32_t) * F);
+    w.slot = (int32_t*)take(sizeof(int32_t) * F);
+    w.act[0] = (int32_t*)take(sizeof(int32_t) * C);
+    w.act[1] = (int32_t*)take(sizeof(int32_t) * C);
+    if (sg.dtype == MPWSD_I8) {
+        w.key32 = (int32_t*)take(sizeof(int32_t) * C);
+        w.metric = (int32_t*)take(sizeof(int32_t) * C);
+        w.z = take(C * (size_t)kpad(N));
+    } else {
+        w.key64 = (uint64_t*)take(sizeof(uint64_t) * C);
+        w.z = take(C * (size_t)N * sizeof(float));
+    }
+    w.cw = take(C * (size_t)(N / 8));
+    w.bytes = off;
+    return w;
+}
+
+int device_cus()
+{
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (!cache[dev]) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+// ---------------------------------------------------------------- compaction
+// One workgroup scans the CRC flags in order, so the failing frames keep
+// their order in the compacted list.
+__global__ __launch_bounds__(1024) void compact_kernel(const uint8_t* __restrict__ crc_ok, int64_t F, int L, int T,
+                                                       int32_t* __restrict__ hdr, int32_t* __restrict__ fid,
+                                                       int32_t* __restrict__ slot, int32_t* __restrict__ stats)
+{
+    __shared__ int wsum[16];
+    __shared__ int base_s;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) base_s = 0;
+    __syncthreads();
+    for (int64_t f0 = 0; f0 < F; f0 += 1024) {
+        const int64_t f = f0 + tid;
+        const bool in = f < F;
+        const bool fail = in && !(crc_ok && crc_ok[f]);
+        const uint64_t bal = __ballot(fail);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wid] = __popcll(bal);
+        __syncthreads();
+        int off = base_s;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        if (fail) {
+            fid[off + before] = (int32_t)f;
+            slot[f] = off + before;
+        } else if (in) {
+            slot[f] = -1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            base_s += tot;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int f2 = base_s;
+        hdr[0] = f2;
+        hdr[1] = 0;
+        hdr[2] = f2 * L;
+        for (int t = 1; t <= T + 1; ++t) hdr[2 + t] = 0;
+        if (stats) atomicAdd(&stats[0], f2);
+    }
+}
+
+__global__ void stats_zero_kernel(int32_t* stats, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) stats[i] = 0;
+}
+
+__global__ void stats_add_kernel(const int32_t* __restrict__ hdr, int T, int32_t* __restrict__ stats)
+{
+    const int t = threadIdx.x;
+    if (t < T) atomicAdd(&stats[1 + t], hdr[2 + t]);
+    if (t == 0) atomicAdd(&stats[1 + T], hdr[1]);
+}
+
+// ---------------------------------------------------------------- init
+// Thread per (frame, path).  Decided frames take their first anchor; the
+// paths of failing frames become columns.
+template <bool FLOAT>
+__global__ void init_kernel(const void* __restrict__ llr, const uint8_t* __restrict__ anchors,
+                            const uint8_t* __restrict__ crc_ok, int64_t F, int L, int T, int N, int KP,
+                            const int32_t* __restrict__ slot, int32_t* __restrict__ act0, int32_t* __restrict__ key32,
+                            uint64_t* __restrict__ key64, int32_t* __restrict__ metric, uint8_t* __restrict__ cw,
+                            void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
+                            int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves)
+{
+    const int NB = N / 8;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < F * L;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = idx / L;
+        const int k = (int)(idx % L);
+        const uint8_t* a = anchors + (size_t)idx * NB;
+        if (out_moves)
+            for (int t = 0; t < T; ++t) out_moves[(size_t)idx * T + t] = -1;
+        const int s = slot[f];
+        if (s < 0) {
+            if (k != 0) continue;
+            for (int b = 0; b < NB; ++b) out_cw[(size_t)f * NB + b] = a[b];
+            if (out_k) out_k[f] = 0;
+            if (out_metric) {
+                if (FLOAT) {
+                    const float* y = (const float*)llr + (size_t)f * N;
+                    float e = 0.0f;
+                    for (int j = 0; j < N; ++j) {
+                        const float x = ((a[j >> 3] >> (j & 7)) & 1) ? -1.0f : 1.0f;
+                        const float dlt = __fsub_rn(y[j], x);
+                        e = __fadd_rn(e, __fmul_rn(dlt, dlt));
+                    }
+                    out_metric[f] = (int32_t)__float_as_uint(e);
+                } else {
+                    const int8_t* q = (const int8_t*)llr + (size_t)f * N;
+                    int e = 0;
+                    for (int j = 0; j < N; ++j) e += ((a[j >> 3] >> (j & 7)) & 1) ? q[j] : 0;
+                    out_metric[f] = e;
+                }
+            }
+            continue;
+        }
+        const int64_t col = (int64_t)s * L + k;
+        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = a[b];
+        act0[col] = (int32_t)col;
+        if (FLOAT) {
+            const float* y = (const float*)llr + (size_t)f * N;
+            float* z = (float*)zbuf + (size_t)col * N;
+            for (int j = 0; j < N; ++j) z[j] = ((a[j >> 3] >> (j & 7)) & 1) ? -y[j] : y[j];
+            key64[col] = ~0ull;
+        } else {
+            const int8_t* q = (const int8_t*)llr + (size_t)f * N;
+            int8_t* z = (int8_t*)zbuf + (size_t)col * KP;
+            int e = 0;
+            for (int j = 0; j < KP; ++j) {
+                const int bit = j < N ? (a[j >> 3] >> (j & 7)) & 1 : 0;
+                const int v = j < N ? q[j] : 0;
+                z[j] = (int8_t)(bit ? -v : v);
+                e += bit ? v : 0;
+            }
+            metric[col] = e;
+            key32[col] = INT_MAX;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- int8 search
+// Unpack 32 bits (LSB first) into 32 bytes of 0/1: every nibble spreads to a
+// dword with one multiply (the four shifted copies do not overlap).
+__device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = (((x >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u;
+}
+
+template <int KP, int NC, int NWAVES>
+__global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
+    const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int N, int64_t P,
+    const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, int32_t* __restrict__ keys)
+{
+    constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
+    constexpr int CT = NWAVES * 16 * NC;        // columns per tile
+    constexpr int HK = KP / 64;                 // MFMAs per 16 x 16 output tile
+    constexpr int NT = NWAVES * WAVE;
+    __shared__ __attribute__((aligned(16))) int8_t lds[2][RC * RS];
+
+    const int n = hdr[2 + t];
+    if (n <= 0) return;
+    const int NB = N / 8;                       // packed bytes per move
+    const int UW = N / 32;                      // 32-bit units per move
+    const int tiles = (n + CT - 1) / CT;
+    const int C = (int)((P + RC - 1) / RC);
+    const int64_t U = (int64_t)tiles * C;
+    int64_t u0 = U * blockIdx.x / gridDim.x;
+    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    if (u0 >= u1) return;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+
+    if (N < KP) {  // positions >= N stay zero for the whole launch
+        for (int e = tid; e < 2 * RC; e += NT) {
+            int8_t* row = &lds[e / RC][(e % RC) * RS];
+            for (int j = N; j < KP; j += 16) *(v4i*)(row + j) = v4i{0, 0, 0, 0};
+        }
+    }
+
+    // this thread's share of a chunk: units of 32 packed bits
+    constexpr int UR = (RC * KP / 32 + NT - 1) / NT;
+    const int units = RC * UW;
+    auto fetch = [&](int chunk, uint32_t (&reg)[UR]) {
+#pragma unroll
+        for (int r = 0; r < UR; ++r) {
+            const int u = tid + r * NT;
+            reg[r] = 0;
+            if (u < units) {
+                const int row = u / UW, wd = u % UW;
+                const int64_t p = (int64_t)chunk * RC + row;
+                if (p < P) reg[r] = *(const uint32_t*)(moves + (size_t)p * NB + 4 * wd);
+            }
+        }
+    };
+    auto store = [&](int b, const uint32_t (&reg)[UR]) {
+#pragma unroll
+        for (int r = 0; r < UR; ++r) {
+            const int u = tid + r * NT;
+            if (u < units) {
+                const int row = u / UW, wd = u % UW;
+                uint32_t o[8];
+                unpack32(reg[r], o);
+                int8_t* dst = &lds[b][row * RS + 32 * wd];
+                *(v4i*)(dst) = v4i{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
+                *(v4i*)(dst + 16) = v4i{(int)o[4], (int)o[5], (int)o[6], (int)o[7]};
+            }
+        }
+    };
+
+    while (u0 < u1) {
+        const int tile = (int)(u0 / C);
+        const int c0 = (int)(u0 % C);
+        const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
+        u0 += c1 - c0;
+
+        // z fragments of this wave's columns; they stay in VGPRs for the sweep
+        v4i zf[NC][HK];
+        int colid[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int pos = tile * CT + wave * 16 * NC + c * 16 + li;
+            colid[c] = pos < n ? act[pos] : -1;
+#pragma unroll
+            for (int h = 0; h < HK; ++h) {
+                if (colid[c] >= 0)
+                    zf[c][h] = *(const v4i*)(z + (size_t)colid[c] * KP + lg * (KP / 4) + 16 * h);
+                else
+                    zf[c][h] = v4i{0, 0, 0, 0};
+            }
+        }
+        int best[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) best[c] = INT_MAX;
+
+        uint32_t reg[UR];
+        fetch(c0, reg);
+        store(0, reg);
+        __syncthreads();
+        for (int k = c0; k < c1; ++k) {
+            const int b = (k - c0) & 1;
+            if (k + 1 < c1) fetch(k + 1, reg);
+            int cm[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cm[c] = INT_MAX;
+#pragma unroll 2
+            for (int tt = 0; tt < RC / 16; ++tt) {
+                v4i af[HK];
+                const int8_t* src = &lds[b][(tt * 16 + li) * RS + lg * (KP / 4)];
+#pragma unroll
+                for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    v4i acc = {0, 0, 0, 0};
+#pragma unroll
+                    for (int h = 0; h < HK; ++h) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc, 0, 0, 0);
+                    cm[c] = min(cm[c], min(acc[0], acc[1]));
+                    cm[c] = min(cm[c], min(acc[2], acc[3]));
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) best[c] = min(best[c], (cm[c] << 16) | k);
+            if (k + 1 < c1) store(b ^ 1, reg);
+            __syncthreads();
+        }
+        // lanes li, li+16, li+32, li+48 hold the same column
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            int v = best[c];
+            v = min(v, __shfl_xor(v, 16));
+            v = min(v, __shfl_xor(v, 32));
+            if (lg == 0 && colid[c] >= 0) atomicMin(&keys[colid[c]], v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- int8 resolve
+// One wave per active column: decode (S_min, chunk), rescore the chunk's 128
+// moves exactly, take the first move attaining S_min, apply it.
+__global__ __launch_bounds__(256) void resolve_i8_kernel(
+    int8_t* __restrict__ z, uint8_t* __restrict__ cw, int32_t* __restrict__ metric, const uint8_t* __restrict__ moves,
+    int N, int KP, int64_t P, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
+    int32_t* __restrict__ hdr, int t, int T, int32_t* __restrict__ keys, const int32_t* __restrict__ fid, int L,
+    int32_t* __restrict__ out_moves)
+{
+    __shared__ int8_t zs[4][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = hdr[2 + t];
+    const int NB = N / 8;
+    const int nwaves = gridDim.x * 4;
+    for (int pos = blockIdx.x * 4 + w; pos < n; pos += nwaves) {
+        const int col = act_in[pos];
+        int key = 0;
+        if (lane == 0) {
+            key = keys[col];
+            keys[col] = INT_MAX;  // ready for the next iteration
+        }
+        key = __shfl(key, 0);
+        const int S = key >> 16;
+        const int chunk = key & 0xFFFF;
+        if (key == INT_MAX || S >= 0) continue;  // no improving move: the path stops
+        int8_t* zc = z + (size_t)col * KP;
+        for (int j = lane; j < N; j += 64) zs[w][j] = zc[j];
+        __builtin_amdgcn_wave_barrier();
+        int sc[2];
+#pragma unroll
+        for (int hlf = 0; hlf < 2; ++hlf) {
+            const int64_t p = (int64_t)chunk * RC + hlf * 64 + lane;
+            int s = INT_MAX;
+            if (p < P) {
+                s = 0;
+                const uint8_t* row = moves + (size_t)p * NB;
+                for (int wd = 0; wd < N / 32; ++wd) {
+                    uint32_t bits = *(const uint32_t*)(row + 4 * wd);
+                    while (bits) {
+                        const int j = 32 * wd + __builtin_ctz(bits);
+                        s += zs[w][j];
+                        bits &= bits - 1;
+                    }
+                }
+            }
+            sc[hlf] = s;
+        }
+        const uint64_t b0 = __ballot(sc[0] == S), b1 = __ballot(sc[1] == S);
+        int64_t pstar = -1;
+        if (b0) pstar = (int64_t)chunk * RC + __builtin_ctzll(b0);
+        else if (b1) pstar = (int64_t)chunk * RC + 64 + __builtin_ctzll(b1);
+        if (pstar < 0) {
+            if (lane == 0) atomicAdd(&hdr[1], 1);
+            continue;
+        }
+        const uint8_t* mv = moves + (size_t)pstar * NB;
+        for (int j = lane; j < N; j += 64)
+            if ((mv[j >> 3] >> (j & 7)) & 1) zc[j] = (int8_t)(-zs[w][j]);
+        for (int bb = lane; bb < NB; bb += 64) cw[(size_t)col * NB + bb] ^= mv[bb];
+        if (lane == 0) {
+            metric[col] += S;
+            if (out_moves) {
+                const int s = col / L, k = col % L;
+                out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)pstar;
+            }
+            const int o = atomicAdd(&hdr[2 + t + 1], 1);
+            act_out[o] = col;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- float search
+// Sequential binary32 sums in ascending position order, on the vector ALUs.
+// Lanes map to columns (64 columns per wave, z columns in LDS as [pos][col]);
+// the supports of a chunk of moves are staged in LDS and read by broadcast.
+__device__ inline uint32_t orderable(float v)
+{
+    const uint32_t u = __float_as_uint(v + 0.0f);  // -0 -> +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// One wave per workgroup: 64 columns, z held in LDS as [position][column]
+// (N <= 256 floats per column), supports of 64 moves staged per step.
+template <int N>
+__global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restrict__ z, const uint8_t* __restrict__ moves,
+                                                          int w, int64_t P, const int32_t* __restrict__ act,
+                                                          const int32_t* __restrict__ hdr, int t,
+                                                          unsigned long long* __restrict__ keys)
+{
+    constexpr int CT = WAVE;  // columns per tile (one per lane)
+    constexpr int MC = 64;    // moves per staged step
+    constexpr int NB = N / 8;
+    __shared__ float zs[N * CT];
+    __shared__ uint8_t sup[MC * (N / 2)];  // supports (w <= N / 2)
+    const int n = hdr[2 + t];
+    if (n <= 0) return;
+    const int lane = threadIdx.x;
+    const int tiles = (n + CT - 1) / CT;
+    const int C = (int)((P + MC - 1) / MC);
+    const int64_t U = (int64_t)tiles * C;
+    int64_t u0 = U * blockIdx.x / gridDim.x;
+    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    while (u0 < u1) {
+        const int tile = (int)(u0 / C);
+        const int c0 = (int)(u0 % C);
+        const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
+        u0 += c1 - c0;
+        const int pos = tile * CT + lane;
+        const int col = pos < n ? act[pos] : -1;
+        __syncthreads();
+        for (int j = 0; j < N; ++j) zs[j * CT + lane] = col >= 0 ? z[(size_t)col * N + j] : 0.0f;
+        unsigned long long best = ~0ull;
+        for (int k = c0; k < c1; ++k) {
+            __syncthreads();
+            {   // lane q extracts the support of move k * MC + q in ascending order
+                const int64_t p = (int64_t)k * MC + lane;
+                if (p < P) {
+                    const uint8_t* row = moves + (size_t)p * NB;
+                    int cnt = 0;
+                    for (int wd = 0; wd < N / 32; ++wd) {
+                        uint32_t bits = *(const uint32_t*)(row + 4 * wd);
+                        while (bits) {
+                            sup[lane * (N / 2) + cnt++] = (uint8_t)(32 * wd + __builtin_ctz(bits));
+                            bits &= bits - 1;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            const int pm = (int)std::min<int64_t>(MC, P - (int64_t)k * MC);
+            for (int q = 0; q < pm; ++q) {
+                const uint8_t* sp = sup + q * (N / 2);
+                float s = zs[sp[0] * CT + lane];
+                for (int i = 1; i < w; ++i) s = __fadd_rn(s, zs[sp[i] * CT + lane]);
+                const unsigned long long kk =
+                    ((unsigned long long)orderable(s) << 32) | (unsigned long long)((int64_t)k * MC + q);
+                best = kk < best ? kk : best;
+            }
+        }
+        if (col >= 0) atomicMin(&keys[col], best);
+    }
+}
+
+__global__ __launch_bounds__(256) void resolve_f32_kernel(
+    float* __restrict__ z, uint8_t* __restrict__ cw, const uint8_t* __restrict__ moves, int N, int64_t P,
+    const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out, int32_t* __restrict__ hdr, int t, int T,
+    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves)
+{
+    const int NB = N / 8;
+    const int n = hdr[2 + t];
+    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < n; pos += gridDim.x * blockDim.x) {
+        const int col = act_in[pos];
+        const unsigned long long key = keys[col];
+        keys[col] = ~0ull;
+        const uint32_t ob = (uint32_t)(key >> 32);
+        // orderable(S) < orderable(+0) <=> S < 0
+        if (key == ~0ull || ob >= 0x80000000u) continue;
+        const int64_t p = (int64_t)(key & 0xFFFFFFFFull);
+        if (p >= P) { atomicAdd(&hdr[1], 1); continue; }
+        const uint8_t* mv = moves + (size_t)p * NB;
+        float* zc = z + (size_t)col * N;
+        for (int j = 0; j < N; ++j)
+            if ((mv[j >> 3] >> (j & 7)) & 1) zc[j] = -zc[j];
+        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] ^= mv[b];
+        if (out_moves) {
+            const int s = col / L, k = col % L;
+            out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)p;
+        }
+        const int o = atomicAdd(&hdr[2 + t + 1], 1);
+        act_out[o] = col;
+    }
+}
+
+// ---------------------------------------------------------------- select
+// Alg. 1 return step: per failing frame, the path of smallest metric, ties
+// to the smallest path index.
+template <bool FLOAT>
+__global__ void select_kernel(const void* __restrict__ llr, const int32_t* __restrict__ hdr,
+                              const int32_t* __restrict__ fid, int L, int N, const int32_t* __restrict__ metric,
+                              const uint8_t* __restrict__ cw, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
+                              int32_t* __restrict__ out_metric)
+{
+    const int f2 = hdr[0];
+    const int NB = N / 8;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < f2; s += gridDim.x * blockDim.x) {
+        const int f = fid[s];
+        int kb = 0;
+        int32_t mb = 0;
+        if (FLOAT) {
+            const float* y = (const float*)llr + (size_t)f * N;
+            float best = 0.0f;
+            for (int k = 0; k < L; ++k) {
+                const uint8_t* c = cw + ((size_t)s * L + k) * NB;
+                float e = 0.0f;
+                for (int j = 0; j < N; ++j) {
+                    const float x = ((c[j >> 3] >> (j & 7)) & 1) ? -1.0f : 1.0f;
+                    const float d = __fsub_rn(y[j], x);
+                    e = __fadd_rn(e, __fmul_rn(d, d));
+                }
+                if (k == 0 || e < best) { best = e; kb = k; }
+            }
+            mb = (int32_t)__float_as_uint(best);
+        } else {
+            mb = metric[(size_t)s * L];
+            for (int k = 1; k < L; ++k) {
+                const int32_t v = metric[(size_t)s * L + k];
+                if (v < mb) { mb = v; kb = k; }
+            }
+        }
+        const uint8_t* c = cw + ((size_t)s * L + kb) * NB;
+        for (int b = 0; b < NB; ++b) out_cw[(size_t)f * NB + b] = c[b];
+        if (out_k) out_k[f] = kb;
+        if (out_metric) out_metric[f] = mb;
+    }
+}
+
+// ---------------------------------------------------------------- launches
+template <int KP>
+void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
+{
+    const int N = 1 << sg.m;
+    constexpr int NC = 8, NW = 4;
+    hipLaunchKernelGGL((search_i8_kernel<KP, NC, NW>), dim3(grid), dim3(NW * WAVE), 0, s, (const int8_t*)w.z,
+                       sg.moves, N, sg.P, w.act[t & 1], w.hdr, t, w.key32);
+}
+
+void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
+{
+    const int wt = 1 << (sg.m - sg.r);
+    const float* z = (const float*)w.z;
+    unsigned long long* keys = (unsigned long long*)w.key64;
+    switch (sg.m) {
+    case 5: hipLaunchKernelGGL(search_f32_kernel<32>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    case 6: hipLaunchKernelGGL(search_f32_kernel<64>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    case 7: hipLaunchKernelGGL(search_f32_kernel<128>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    default: hipLaunchKernelGGL(search_f32_kernel<256>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    }
+}
+
+int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipEvent_t* ev,
+                hipStream_t s)
+{
+    const int N = 1 << sg.m, KP = kpad(N);
+    const bool fl = sg.dtype == MPWSD_F32;
+    const int cus = device_cus();
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, sg.crc_ok, sg.F, L, T, w.hdr, w.fid, w.slot, stats);
+    {
+        const int64_t work = sg.F * L;
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
+        if (fl)
+            hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.crc_ok, sg.F, L,
+                               T, N, KP, w.slot, w.act[0], w.key32, w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                               sg.out_metric, sg.out_moves);
+        else
+            hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.crc_ok, sg.F,
+                               L, T, N, KP, w.slot, w.act[0], w.key32, w.key64, w.metric, w.cw, w.z, sg.out_cw,
+                               sg.out_k, sg.out_metric, sg.out_moves);
+    }
+    const int resolve_blocks = cus * 8;
+    for (int t = 0; t < T; ++t) {
+        if (ev) (void)hipEventRecord(ev[2 * t], s);
+        if (fl) {
+            launch_search_f32(w, sg, t, s, cus * 4);
+            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+            hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves,
+                               N, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
+                               (unsigned long long*)w.key64, w.fid, L, sg.out_moves);
+        } else {
+            switch (KP) {
+            case 64: launch_search_i8<64>(w, sg, t, s, cus * 2); break;
+            case 128: launch_search_i8<128>(w, sg, t, s, cus * 2); break;
+            default: launch_search_i8<256>(w, sg, t, s, cus * 2); break;
+            }
+            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+            hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
+                               sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, w.key32, w.fid,
+                               L, sg.out_moves);
+        }
+    }
+    {
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
+        if (fl)
+            hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
+                               w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
+        else
+            hipLaunchKernelGGL(select_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
+                               w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
+    }
+    if (stats) hipLaunchKernelGGL(stats_add_kernel, dim3(1), dim3(128), 0, s, w.hdr, T, stats);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch: %s", hipGetErrorString(e));
+    return MPWSD_OK;
+}
+
+int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
+{
+    using mpwsd::fail;
+    if (!segs || nseg < 1) return fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: need at least one segment");
+    if (L < 1 || L > 32) return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_decode_batch: need 1 <= L <= 32 (L=%d)", L);
+    if (T < 1 || T > 64) return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_decode_batch: need 1 <= T <= 64 (T=%d)", T);
+    for (int i = 0; i < nseg; ++i) {
+        const mpwsd_segment& s = segs[i];
+        if (s.m < 5 || s.m > 8 || s.r < 1 || s.r >= s.m)
+            return fail(MPWSD_ERR_UNSUPPORTED, "segment %d: need 1 <= r < m, 5 <= m <= 8", i);
+        if (s.dtype != MPWSD_I8 && s.dtype != MPWSD_F32) return fail(MPWSD_ERR_ARG, "segment %d: bad dtype", i);
+        if (s.dtype != segs[0].dtype) return fail(MPWSD_ERR_ARG, "segment %d: all segments need the same dtype", i);
+        if (s.F < 0) return fail(MPWSD_ERR_ARG, "segment %d: F < 0", i);
+        if (s.P != mpwsd::rm_min_weight_count(s.r, s.m))
+            return fail(MPWSD_ERR_ARG, "segment %d: P=%lld is not the move count %lld of RM(%d,%d)", i,
+                        (long long)s.P, (long long)mpwsd::rm_min_weight_count(s.r, s.m), s.r, s.m);
+        if (s.F * (int64_t)L > INT_MAX / 2) return fail(MPWSD_ERR_UNSUPPORTED, "segment %d: F * L too large", i);
+        if (check_ptrs && s.F > 0 && (!s.moves || !s.llr || !s.anchors || !s.out_cw))
+            return fail(MPWSD_ERR_ARG, "segment %d: null pointer", i);
+        if (check_ptrs && (reinterpret_cast<uintptr_t>(s.moves) & 3u) != 0)
+            return fail(MPWSD_ERR_ARG, "segment %d: moves must be 4-byte aligned", i);
+    }
+    return MPWSD_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T)
+{
+    mpwsd::clear_error();
+    if (validate(segs, nseg, L, T, false) != MPWSD_OK) return 0;
+    size_t tot = 0;
+    for (int i = 0; i < nseg; ++i) tot += carve(segs[i], L, T, nullptr).bytes;
+    return tot;
+}
+
+namespace {
+int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t ws_bytes, int32_t* stats,
+           hipEvent_t* events, hipStream_t stream)
+{
+    int rc = validate(segs, nseg, L, T, true);
+    if (rc != MPWSD_OK) return rc;
+    size_t need = 0;
+    for (int i = 0; i < nseg; ++i) need += carve(segs[i], L, T, nullptr).bytes;
+    if (!ws || ws_bytes < need)
+        return mpwsd::fail(MPWSD_ERR_SIZE, "mpwsd_decode_batch: workspace needs %zu bytes, got %zu", need, ws_bytes);
+    if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+        return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: workspace must be 256-byte aligned");
+    if (stats) hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, stream, stats, 2 + T);
+    uint8_t* base = (uint8_t*)ws;
+    for (int i = 0; i < nseg; ++i) {
+        SegWs w = carve(segs[i], L, T, base);
+        base += w.bytes;
+        if (segs[i].F == 0) continue;
+        rc = run_segment(segs[i], L, T, w, stats, events ? events + (size_t)2 * T * i : nullptr, stream);
+        if (rc != MPWSD_OK) return rc;
+    }
+    return MPWSD_OK;
+}
+}  // namespace
+
+extern "C" int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t ws_bytes,
+                                  int32_t* stats, hipStream_t stream)
+{
+    mpwsd::clear_error();
+    return decode(segs, nseg, L, T, ws, ws_bytes, stats, nullptr, stream);
+}
+
+extern "C" int mpwsd_decode_batch_timed(const mpwsd_segment* segs, int nseg, int L, int T, void* ws,
+                                        size_t ws_bytes, int32_t* stats, hipEvent_t* events, hipStream_t stream)
+{
+    mpwsd::clear_error();
+    if (!events) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch_timed: events is NULL");
+    return decode(segs, nseg, L, T, ws, ws_bytes, stats, events, stream);
+}

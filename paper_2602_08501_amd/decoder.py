@@ -1,0 +1,114 @@
+"""Thin torch-backed driver over the C-ABI: owns device buffers, calls the
+library.  PyTorch is used for device memory and streams only."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MPWSD_F32, MPWSD_I8, Segment, check
+
+
+def build_moves_host(r: int, m: int) -> np.ndarray:
+    """Move table S_1(0) of RM(r, m), [P][N/8] uint8 (host, via the library)."""
+    rc, P, N, w = _lib.mpwsd_build_moves(r, m, None, 0)
+    check(rc)
+    buf = np.zeros((P, N // 8), np.uint8)
+    rc, P, N, w = _lib.mpwsd_build_moves(r, m, buf.ctypes.data, buf.nbytes)
+    check(rc)
+    return buf
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Code:
+    """Device-resident move table of RM(r, m)."""
+
+    def __init__(self, r: int, m: int, device="cuda:0"):
+        self.r, self.m, self.N = r, m, 1 << m
+        host = build_moves_host(r, m)
+        self.P = host.shape[0]
+        self.w = 1 << (m - r)
+        self.moves = torch.from_numpy(host).to(device)
+        self.K = sum(math.comb(m, d) for d in range(r + 1))
+
+
+def quantize(y: torch.Tensor, scale: float, bad: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    q = torch.empty(y.shape, dtype=torch.int8, device=y.device)
+    check(_lib.mpwsd_quantize_llr(y.data_ptr(), y.numel(), float(np.float32(scale)), q.data_ptr(),
+                                  _ptr(bad), _stream(stream)))
+    return q
+
+
+def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: int = 0x43,
+           out=None, stream=None, want_pm: bool = False):
+    F = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        out = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
+               "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)}
+        if want_pm:
+            out["pm"] = torch.empty((F, L), dtype=torch.int32, device=dev)
+    dtype = MPWSD_I8 if llr.dtype == torch.int8 else MPWSD_F32
+    check(_lib.mpwsd_stage1_scl(code.r, code.m, crc_len, crc_poly, L, llr.data_ptr(), dtype, F,
+                                out["anchors"].data_ptr(), out["crc_ok"].data_ptr(),
+                                _ptr(out.get("pm")), _stream(stream)))
+    return out
+
+
+class Stage2:
+    """Buffers and one call of mpwsd_decode_batch for a fixed batch shape."""
+
+    def __init__(self, codes_F, L: int, T: int, dtype: str, device="cuda:0", want_moves=True):
+        """codes_F: list of (Code, F) per segment."""
+        self.L, self.T, self.device = L, T, device
+        self.dt = MPWSD_I8 if dtype == "i8" else MPWSD_F32
+        self.codes_F = codes_F
+        self.outs = []
+        for code, F in codes_F:
+            o = {"cw": torch.empty((F, code.N // 8), dtype=torch.uint8, device=device),
+                 "k": torch.empty(F, dtype=torch.int32, device=device),
+                 "metric": torch.empty(F, dtype=torch.int32, device=device)}
+            if want_moves:
+                o["moves"] = torch.empty((F, L, T), dtype=torch.int32, device=device)
+            self.outs.append(o)
+        self.stats = torch.zeros(2 + T, dtype=torch.int32, device=device)
+        need = _lib.mpwsd_workspace_bytes(self._segs([None] * len(codes_F), [None] * len(codes_F),
+                                                     [None] * len(codes_F)), L, T)
+        if need == 0:
+            raise _lib.MpwsdError(-1, _lib.last_error())
+        self.ws = torch.empty(need + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr, self.ws_bytes = self.ws.data_ptr() + off, need
+
+    def _segs(self, llrs, anchors, crc_oks):
+        segs = []
+        for (code, F), llr, anc, ok, o in zip(self.codes_F, llrs, anchors, crc_oks,
+                                              self.outs or [None] * len(self.codes_F)):
+            segs.append(Segment(code.r, code.m, code.moves.data_ptr(), code.P, _ptr(llr), self.dt, F,
+                                _ptr(anc), _ptr(ok), _ptr(o["cw"]) if o else None,
+                                _ptr(o["k"]) if o else None, _ptr(o["metric"]) if o else None,
+                                _ptr(o.get("moves")) if o else None))
+        return segs
+
+    def run(self, llrs, anchors, crc_oks, stream=None, events=None):
+        """events: optional list of 2 * T * nseg recorded torch.cuda.Event
+        (enable_timing=True); re-recorded around every search launch."""
+        segs = self._segs(llrs, anchors, crc_oks)
+        if events is None:
+            check(_lib.mpwsd_decode_batch(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
+                                          self.stats.data_ptr(), _stream(stream)))
+        else:
+            check(_lib.mpwsd_decode_batch_timed(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
+                                                self.stats.data_ptr(), [e.cuda_event for e in events],
+                                                _stream(stream)))
+        return self.outs

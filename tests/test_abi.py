@@ -1,0 +1,115 @@
+"""The C-ABI library on the CPU: it loads, exports every declared call, its
+host-side move table is byte-identical to the oracle's, and argument errors
+are reported before anything is enqueued (none of these touch a GPU)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_08501_amd import _lib
+from paper_2602_08501_amd._lib import Segment
+
+
+def test_library_exports_every_declared_call():
+    lib = _lib.load()
+    names = _lib.header_functions()
+    assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_quantize_llr",
+                          "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
+                          "mpwsd_decode_batch_timed"}
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("r,m", [(1, 5), (2, 6), (1, 7), (2, 7), (3, 7), (4, 7), (1, 6)])
+def test_move_table_matches_oracle(r, m):
+    rc, P, N, w = _lib.mpwsd_build_moves(r, m, None, 0)
+    assert rc == 0 and N == 1 << m and w == 1 << (m - r)
+    buf = np.zeros((P, N // 8), np.uint8)
+    rc, *_ = _lib.mpwsd_build_moves(r, m, buf.ctypes.data, buf.nbytes)
+    assert rc == 0
+    supp, w2 = oracle.moves(r, m)
+    assert np.array_equal(buf, oracle.pack_supports(m, supp))
+
+
+@pytest.mark.slow
+def test_move_table_matches_oracle_rm38():
+    rc, P, N, w = _lib.mpwsd_build_moves(3, 8, None, 0)
+    assert P == 777240
+    buf = np.zeros((P, N // 8), np.uint8)
+    assert _lib.mpwsd_build_moves(3, 8, buf.ctypes.data, buf.nbytes)[0] == 0
+    supp, _ = oracle.moves(3, 8)
+    assert np.array_equal(buf, oracle.pack_supports(8, supp))
+
+
+def test_build_moves_errors():
+    rc, *_ = _lib.mpwsd_build_moves(0, 6, None, 0)
+    assert rc == _lib.MPWSD_ERR_UNSUPPORTED and "r" in _lib.last_error()
+    rc, *_ = _lib.mpwsd_build_moves(6, 6, None, 0)
+    assert rc == _lib.MPWSD_ERR_UNSUPPORTED
+    buf = np.zeros(10, np.uint8)
+    rc, P, N, w = _lib.mpwsd_build_moves(2, 6, buf.ctypes.data, buf.nbytes)
+    assert rc == _lib.MPWSD_ERR_SIZE and P == 2604
+    assert "need" in _lib.last_error()
+
+
+def _seg(**kw):
+    d = dict(r=3, m=7, moves=0x1000, P=94488, llr=0x2000, dtype=0, F=16, anchors=0x3000,
+             crc_ok=None, out_cw=0x4000, out_k=None, out_metric=None, out_moves=None)
+    d.update(kw)
+    return Segment(**d)
+
+
+def test_decode_batch_validates_before_enqueue():
+    ok = _lib.mpwsd_workspace_bytes([_seg()], 8, 8)
+    assert ok > 0
+    cases = [
+        ([_seg(P=8128)], 8, 8, _lib.MPWSD_ERR_ARG),          # not the RM(3,7) move count
+        ([_seg(m=9, r=3)], 8, 8, _lib.MPWSD_ERR_UNSUPPORTED),
+        ([_seg()], 0, 8, _lib.MPWSD_ERR_UNSUPPORTED),
+        ([_seg()], 33, 8, _lib.MPWSD_ERR_UNSUPPORTED),
+        ([_seg()], 8, 0, _lib.MPWSD_ERR_UNSUPPORTED),
+        ([_seg()], 8, 65, _lib.MPWSD_ERR_UNSUPPORTED),
+        ([_seg(dtype=7)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(), _seg(dtype=1)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(F=-1)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(llr=None)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(moves=0x1001)], 8, 8, _lib.MPWSD_ERR_ARG),
+    ]
+    for segs, L, T, code in cases:
+        if segs[-1].llr and segs[-1].moves % 4 == 0:  # size query ignores pointers
+            assert _lib.mpwsd_workspace_bytes(segs, L, T) == 0
+        assert _lib.mpwsd_decode_batch(segs, L, T, 0x10000, 1 << 40, None, None) == code, _lib.last_error()
+    # workspace too small / missing / misaligned
+    assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10000, ok - 1, None, None) == _lib.MPWSD_ERR_SIZE
+    assert _lib.mpwsd_decode_batch([_seg()], 8, 8, None, ok, None, None) == _lib.MPWSD_ERR_SIZE
+    assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10010, ok, None, None) == _lib.MPWSD_ERR_ARG
+
+
+def test_stage1_validates_before_enqueue():
+    A = 0x1000
+    cases = [
+        (dict(r=3, m=9), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(L=6), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(L=64), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(r=1, m=5, L=128), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(crc_len=17), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(crc_poly=0x03), _lib.MPWSD_ERR_ARG),
+        (dict(dtype=5), _lib.MPWSD_ERR_ARG),
+        (dict(F=-2), _lib.MPWSD_ERR_ARG),
+        (dict(anchors=None), _lib.MPWSD_ERR_ARG),
+        (dict(anchors=A + 2), _lib.MPWSD_ERR_ARG),
+    ]
+    for kw, code in cases:
+        a = dict(r=3, m=7, crc_len=6, crc_poly=0x43, L=8, llr=A, dtype=0, F=4, anchors=A, crc_ok=A, pm=None,
+                 stream=None)
+        a.update(kw)
+        rc = _lib.mpwsd_stage1_scl(a["r"], a["m"], a["crc_len"], a["crc_poly"], a["L"], a["llr"], a["dtype"],
+                                   a["F"], a["anchors"], a["crc_ok"], a["pm"], a["stream"])
+        assert rc == code, (kw, _lib.last_error())
+        assert _lib.last_error()
+    # nothing to do is not an error
+    assert _lib.mpwsd_stage1_scl(3, 7, 6, 0x43, 8, None, 0, 0, None, None, None, None) == 0
+    assert _lib.mpwsd_quantize_llr(None, 0, 1.0, None, None, None) == 0
+    assert _lib.mpwsd_quantize_llr(None, 5, 1.0, None, None, None) == _lib.MPWSD_ERR_ARG
+    assert _lib.mpwsd_quantize_llr(A, 5, float("inf"), A, None, None) == _lib.MPWSD_ERR_ARG
