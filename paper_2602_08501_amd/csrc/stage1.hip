@@ -62,35 +62,132 @@ template <int NW> __device__ inline void polar_bits(uint32_t (&w)[NW], int lev)
     }
 }
 
-template <int M, bool FLOAT>
-__global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F, int L,
+template <int M, int L, bool FLOAT> struct Scl {
+    using A = Arith<FLOAT>;
+    using V = typename A::V;
+    using S = typename A::S;
+    static constexpr int N = 1 << M;
+    static constexpr int NW = N / 32;    // words of decided bits per path
+    static constexpr int G = WAVE / L;   // frames per wave
+
+    struct Smem {
+        S buf[(N - 1) * WAVE];  // level l of lane x: rows [2^l - 1, 2^(l+1) - 1), column x
+        S ch[G * N];            // channel LLRs of the wave's frames
+        uint64_t key[2 * WAVE];
+        int sel[WAVE];
+        V cpm[WAVE];
+        int cvalid[WAVE];
+        uint64_t ptr[WAVE];
+        uint32_t ub[NW * WAVE];
+    };
+
+    // Recompute level LEV of this lane's path from level LEV + 1 (the
+    // channel when LEV = M - 1): f for a left child, g for a right child with
+    // the left sibling's bits re-encoded.
+    template <int LEV>
+    __device__ static V level(Smem& sm, int lane, int gbase, int i, bool use_g, uint64_t ptrs, const uint32_t (&ub)[NW])
+    {
+        constexpr int n = 1 << LEV;
+        constexpr int PW = (n + 31) / 32;
+        uint32_t ps[PW];
+        if (use_g) {
+            const int st = i - n;
+            if (n < 32) {
+                ps[0] = (ub[st >> 5] >> (st & 31)) & ((1u << (n & 31)) - 1u);
+            } else {
+#pragma unroll
+                for (int w = 0; w < PW; ++w) ps[w] = ub[(st >> 5) + w];
+            }
+            polar_bits(ps, LEV);
+        }
+        const S* par;
+        int stride;
+        if (LEV + 1 == M) {
+            par = sm.ch + (lane / L) * N;
+            stride = 1;
+        } else {
+            const int owner = gbase + (int)((ptrs >> (8 * (LEV + 1))) & 0xFF);
+            par = sm.buf + (2 * n - 1) * WAVE + owner;
+            stride = WAVE;
+        }
+        S* out = sm.buf + (n - 1) * WAVE + lane;
+        V o = 0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            const V a = (V)par[k * stride];
+            const V b = (V)par[(k + n) * stride];
+            if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
+            else o = f_minsum(a, b);
+            out[k * WAVE] = (S)o;
+        }
+        return o;
+    }
+
+    template <int D>
+    __device__ static V run(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
+    {
+        V lam = level<D>(sm, lane, gbase, i, i > 0, ptrs, ub);
+        ptrs = (ptrs & ~(0xFFull << (8 * D))) | ((uint64_t)slot << (8 * D));
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (D > 0) {
+            lam = run_f<D - 1>(sm, lane, gbase, i, slot, ptrs, ub);
+        }
+        return lam;
+    }
+
+    template <int D>
+    __device__ static V run_f(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
+    {
+        V lam = level<D>(sm, lane, gbase, i, false, ptrs, ub);
+        ptrs = (ptrs & ~(0xFFull << (8 * D))) | ((uint64_t)slot << (8 * D));
+        __builtin_amdgcn_wave_barrier();
+        if constexpr (D > 0) lam = run_f<D - 1>(sm, lane, gbase, i, slot, ptrs, ub);
+        return lam;
+    }
+
+    __device__ static V leaf(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
+    {
+        const int d = (i == 0) ? M - 1 : __builtin_ctz(i);
+        switch (d) {
+        case 0: return run<0>(sm, lane, gbase, i, slot, ptrs, ub);
+        case 1: return run<1>(sm, lane, gbase, i, slot, ptrs, ub);
+        case 2: return run<2>(sm, lane, gbase, i, slot, ptrs, ub);
+        case 3: return run<3>(sm, lane, gbase, i, slot, ptrs, ub);
+        case 4: return run<4>(sm, lane, gbase, i, slot, ptrs, ub);
+        case 5: if constexpr (M > 5) return run<5>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
+        case 6: if constexpr (M > 6) return run<6>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
+        default: if constexpr (M > 7) return run<7>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
+        }
+    }
+};
+
+template <int M, int L, bool FLOAT>
+__global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F,
                                                    uint64_t info0, uint64_t info1, uint64_t info2, uint64_t info3,
                                                    int crc_len, uint32_t crc_poly,
                                                    uint8_t* __restrict__ anchors, uint8_t* __restrict__ crc_ok,
                                                    int32_t* __restrict__ pm_out)
 {
-    using A = Arith<FLOAT>;
-    using V = typename A::V;
-    using S = typename A::S;
-    constexpr int N = 1 << M;
-    constexpr int NW = N / 32;  // words of decided bits per path
-    __shared__ S buf[(N - 1) * WAVE];
-    __shared__ uint64_t key_s[2 * WAVE];
-    __shared__ int sel_s[WAVE];
-    __shared__ V cpm_s[WAVE];
-    __shared__ uint64_t ptr_s[WAVE];
-    __shared__ uint32_t ub_s[NW * WAVE];
-    __shared__ int valid_s[WAVE];
-    __shared__ int cvalid_s[WAVE];
+    using K = Scl<M, L, FLOAT>;
+    using A = typename K::A;
+    using V = typename K::V;
+    using S = typename K::S;
+    constexpr int N = K::N, NW = K::NW, G = K::G;
+    __shared__ typename K::Smem sm;
 
     const int lane = threadIdx.x;
-    const int lgL = __builtin_ctz(L);
-    const int slot = lane & (L - 1);
+    const int slot = lane % L;
     const int gbase = lane - slot;  // first lane of this frame group
-    const int64_t frame = (int64_t)blockIdx.x * (WAVE >> lgL) + (lane >> lgL);
+    const int64_t frame = (int64_t)blockIdx.x * G + lane / L;
     const bool live = frame < F;
-    const int64_t fr = live ? frame : 0;
     const uint64_t info[4] = {info0, info1, info2, info3};
+
+    // stage the channel values of the wave's frames (coalesced)
+    for (int e = lane; e < G * N; e += WAVE) {
+        const int64_t fr = (int64_t)blockIdx.x * G + e / N;
+        sm.ch[e] = (S)(fr < F ? A::load_ch(llr, fr * N + e % N) : (V)0);
+    }
+    __syncthreads();
 
     V pm = 0;
     bool valid = (slot == 0);
@@ -98,53 +195,11 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     uint32_t ub[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) ub[i] = 0;
+#pragma unroll
     for (int l = 0; l < M; ++l) ptrs |= (uint64_t)slot << (8 * l);
 
     for (int i = 0; i < N; ++i) {
-        const int d = (i == 0) ? M - 1 : __builtin_ctz(i);
-        V lam = 0;
-        for (int lev = d; lev >= 0; --lev) {
-            const int n = 1 << lev;
-            const int obase = n - 1;
-            const bool use_g = (lev == d) && (i > 0);
-            uint32_t ps[NW > 0 ? NW : 1];
-            if (use_g) {
-                // left sibling covers leaves [i - n, i): its decided bits, re-encoded
-                const int st = i - n;
-                if (n < 32) {
-                    ps[0] = (ub[st >> 5] >> (st & 31)) & ((1u << n) - 1u);
-                } else {
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) ps[w] = (w < n / 32) ? ub[(st >> 5) + w] : 0u;
-                }
-                polar_bits(ps, lev);
-            }
-            if (lev + 1 == M) {
-                const int64_t cb = fr * N;
-                for (int k = 0; k < n; ++k) {
-                    V a = A::load_ch(llr, cb + k), b = A::load_ch(llr, cb + k + n);
-                    V o;
-                    if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
-                    else o = f_minsum(a, b);
-                    buf[(obase + k) * WAVE + lane] = (S)o;
-                    lam = o;
-                }
-            } else {
-                const int owner = gbase + (int)((ptrs >> (8 * (lev + 1))) & 0xFF);
-                const int pbase = 2 * n - 1;
-                for (int k = 0; k < n; ++k) {
-                    V a = (V)buf[(pbase + k) * WAVE + owner];
-                    V b = (V)buf[(pbase + k + n) * WAVE + owner];
-                    V o;
-                    if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
-                    else o = f_minsum(a, b);
-                    buf[(obase + k) * WAVE + lane] = (S)o;
-                    lam = o;
-                }
-            }
-            ptrs = (ptrs & ~(0xFFull << (8 * lev))) | ((uint64_t)slot << (8 * lev));
-            __builtin_amdgcn_wave_barrier();
-        }
+        const V lam = K::leaf(sm, lane, gbase, i, slot, ptrs, ub);
         const bool frozen = ((info[i >> 6] >> (i & 63)) & 1ull) == 0;
         const V mag = lam < 0 ? -lam : lam;
         const int hd = lam < 0 ? 1 : 0;
@@ -161,44 +216,48 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
         for (int u = 0; u < 2; ++u) {
             const uint64_t hi = valid ? (uint64_t)A::key_bits(cp[u]) : 0xFFFFFFFFull;
             key[u] = (hi << 8) | (uint64_t)(2 * slot + u);
-            key_s[2 * lane + u] = key[u];
+            sm.key[2 * lane + u] = key[u];
         }
-        ptr_s[lane] = ptrs;
-        valid_s[lane] = valid ? 1 : 0;
+        sm.ptr[lane] = ptrs;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) ub_s[w * WAVE + lane] = ub[w];
+        for (int w = 0; w < NW; ++w) sm.ub[w * WAVE + lane] = ub[w];
         __syncthreads();
-        int rank[2] = {0, 0};
+        int rank0 = 0, rank1 = 0;
+#pragma unroll
         for (int c = 0; c < 2 * L; ++c) {
-            const uint64_t o = key_s[2 * gbase + c];
-            rank[0] += o < key[0];
-            rank[1] += o < key[1];
+            const uint64_t o = sm.key[2 * gbase + c];
+            rank0 += o < key[0];
+            rank1 += o < key[1];
         }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (rank[u] < L) {
-                sel_s[gbase + rank[u]] = 2 * slot + u;
-                cpm_s[gbase + rank[u]] = cp[u];
-                cvalid_s[gbase + rank[u]] = valid ? 1 : 0;
-            }
+        if (rank0 < L) {
+            sm.sel[gbase + rank0] = 2 * slot;
+            sm.cpm[gbase + rank0] = cp[0];
+            sm.cvalid[gbase + rank0] = valid ? 1 : 0;
+        }
+        if (rank1 < L) {
+            sm.sel[gbase + rank1] = 2 * slot + 1;
+            sm.cpm[gbase + rank1] = cp[1];
+            sm.cvalid[gbase + rank1] = valid ? 1 : 0;
+        }
         __syncthreads();
-        const int c = sel_s[lane];
+        const int c = sm.sel[lane];
         const int par = gbase + (c >> 1);
-        pm = cpm_s[lane];
-        valid = cvalid_s[lane] != 0;
-        ptrs = ptr_s[par];
+        pm = sm.cpm[lane];
+        valid = sm.cvalid[lane] != 0;
+        ptrs = sm.ptr[par];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) ub[w] = ub_s[w * WAVE + par];
+        for (int w = 0; w < NW; ++w) ub[w] = sm.ub[w * WAVE + par];
         ub[i >> 5] |= (uint32_t)(c & 1) << (i & 31);
         __syncthreads();
     }
 
     // final order: (PM, slot) ascending
     const uint64_t fkey = ((uint64_t)(valid ? A::key_bits(pm) : 0xFFFFFFFFu) << 8) | (uint64_t)slot;
-    key_s[lane] = fkey;
+    sm.key[lane] = fkey;
     __syncthreads();
     int rank = 0;
-    for (int c = 0; c < L; ++c) rank += key_s[gbase + c] < fkey;
+#pragma unroll
+    for (int c = 0; c < L; ++c) rank += sm.key[gbase + c] < fkey;
     uint32_t cw[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) cw[w] = ub[w];
@@ -243,14 +302,28 @@ __global__ void quantize_kernel(const float* __restrict__ y, int64_t n, float s,
     }
 }
 
+template <int M, int L, bool FL>
+void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, uint32_t poly, uint8_t* anchors,
+                 uint8_t* crc_ok, int32_t* pm, hipStream_t s)
+{
+    constexpr int64_t per = WAVE / L;
+    const int64_t blocks = (F + per - 1) / per;
+    hipLaunchKernelGGL((scl_kernel<M, L, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, info[0], info[1],
+                       info[2], info[3], crc_len, poly, anchors, crc_ok, pm);
+}
+
 template <int M, bool FL>
 void launch_scl(const void* llr, int64_t F, int L, const uint64_t* info, int crc_len, uint32_t poly,
                 uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, hipStream_t s)
 {
-    const int64_t per = WAVE / L;
-    const int64_t blocks = (F + per - 1) / per;
-    hipLaunchKernelGGL((scl_kernel<M, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, L, info[0], info[1],
-                       info[2], info[3], crc_len, poly, anchors, crc_ok, pm);
+    switch (L) {
+    case 1: launch_scl3<M, 1, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    case 2: launch_scl3<M, 2, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    case 4: launch_scl3<M, 4, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    case 8: launch_scl3<M, 8, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    case 16: launch_scl3<M, 16, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    default: launch_scl3<M, 32, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    }
 }
 
 }  // namespace

@@ -45,11 +45,11 @@ struct SegWs {
     int32_t* fid;     // [F] compacted failing frames
     int32_t* slot;    // [F] frame -> compacted slot (-1 when decided)
     int32_t* act[2];  // [F*L] active column lists (ping-pong)
-    int32_t* key32;   // [F*L] int8 form: (S << 16 | chunk) minima
-    uint64_t* key64;  // [F*L] float form: (orderable S << 32 | p) minima
+    uint64_t* key64;  // [F*L] per-column minimum: int8 (S << 32 | p) as int64,
+                      // float (orderable(S) << 32 | p) as uint64
     int32_t* metric;  // [F*L] int8: M; float: unused
     uint8_t* cw;      // [F*L][N/8] centres
-    void* z;          // [F*L][KP] int8 or [F*L][N] float
+    void* z;          // [F*L][KP] int8 -z (negated) or [F*L][N] float z
     size_t bytes;
 };
 
@@ -69,12 +69,11 @@ SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
     w.slot = (int32_t*)take(sizeof(int32_t) * F);
     w.act[0] = (int32_t*)take(sizeof(int32_t) * C);
     w.act[1] = (int32_t*)take(sizeof(int32_t) * C);
+    w.key64 = (uint64_t*)take(sizeof(uint64_t) * C);
     if (sg.dtype == MPWSD_I8) {
-        w.key32 = (int32_t*)take(sizeof(int32_t) * C);
         w.metric = (int32_t*)take(sizeof(int32_t) * C);
         w.z = take(C * (size_t)kpad(N));
     } else {
-        w.key64 = (uint64_t*)take(sizeof(uint64_t) * C);
         w.z = take(C * (size_t)N * sizeof(float));
     }
     w.cw = take(C * (size_t)(N / 8));
@@ -100,48 +99,40 @@ int device_cus()
 }
 
 // ---------------------------------------------------------------- compaction
-// One workgroup scans the CRC flags in order, so the failing frames keep
-// their order in the compacted list.
-__global__ __launch_bounds__(1024) void compact_kernel(const uint8_t* __restrict__ crc_ok, int64_t F, int L, int T,
-                                                       int32_t* __restrict__ hdr, int32_t* __restrict__ fid,
-                                                       int32_t* __restrict__ slot, int32_t* __restrict__ stats)
+// Failing frames are appended to the compacted list with one atomic per
+// workgroup (their order in the list is irrelevant: every frame is decoded
+// independently and results are written per frame).
+__global__ void hdr_zero_kernel(int32_t* __restrict__ hdr, int n)
 {
-    __shared__ int wsum[16];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) hdr[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ crc_ok, int64_t F,
+                                                      int32_t* __restrict__ hdr, int32_t* __restrict__ fid,
+                                                      int32_t* __restrict__ slot)
+{
+    __shared__ int wsum[4];
     __shared__ int base_s;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) base_s = 0;
+    const int64_t f = (int64_t)blockIdx.x * 256 + tid;
+    const bool in = f < F;
+    const bool fail = in && !(crc_ok && crc_ok[f]);
+    const uint64_t bal = __ballot(fail);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wid] = __popcll(bal);
     __syncthreads();
-    for (int64_t f0 = 0; f0 < F; f0 += 1024) {
-        const int64_t f = f0 + tid;
-        const bool in = f < F;
-        const bool fail = in && !(crc_ok && crc_ok[f]);
-        const uint64_t bal = __ballot(fail);
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0) wsum[wid] = __popcll(bal);
-        __syncthreads();
-        int off = base_s;
-        for (int w = 0; w < wid; ++w) off += wsum[w];
-        if (fail) {
-            fid[off + before] = (int32_t)f;
-            slot[f] = off + before;
-        } else if (in) {
-            slot[f] = -1;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int tot = 0;
-            for (int w = 0; w < 16; ++w) tot += wsum[w];
-            base_s += tot;
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
-        const int f2 = base_s;
-        hdr[0] = f2;
-        hdr[1] = 0;
-        hdr[2] = f2 * L;
-        for (int t = 1; t <= T + 1; ++t) hdr[2 + t] = 0;
-        if (stats) atomicAdd(&stats[0], f2);
+        const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base_s = tot ? atomicAdd(&hdr[0], tot) : 0;
+    }
+    __syncthreads();
+    int off = base_s + before;
+    for (int w = 0; w < wid; ++w) off += wsum[w];
+    if (fail) {
+        fid[off] = (int32_t)f;
+        slot[f] = off;
+    } else if (in) {
+        slot[f] = -1;
     }
 }
 
@@ -158,85 +149,116 @@ __global__ void stats_add_kernel(const int32_t* __restrict__ hdr, int T, int32_t
 }
 
 // ---------------------------------------------------------------- init
-// Thread per (frame, path).  Decided frames take their first anchor; the
-// paths of failing frames become columns.
+// Thread per (frame, path, 16 positions).  Decided frames take their first
+// anchor; the paths of failing frames become columns: centre bits, z and the
+// metric M(c) = sum_{c_j = 1} q_j (int8 form).  Thread 0 also publishes the
+// number of columns for the first search.
 template <bool FLOAT>
-__global__ void init_kernel(const void* __restrict__ llr, const uint8_t* __restrict__ anchors,
-                            const uint8_t* __restrict__ crc_ok, int64_t F, int L, int T, int N, int KP,
-                            const int32_t* __restrict__ slot, int32_t* __restrict__ act0, int32_t* __restrict__ key32,
-                            uint64_t* __restrict__ key64, int32_t* __restrict__ metric, uint8_t* __restrict__ cw,
-                            void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
-                            int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves)
+__global__ __launch_bounds__(256) void init_kernel(
+    const void* __restrict__ llr, const uint8_t* __restrict__ anchors, int64_t F, int L, int T, int N, int KP,
+    int32_t* __restrict__ hdr, const int32_t* __restrict__ slot, int32_t* __restrict__ act0,
+    uint64_t* __restrict__ key64, int32_t* __restrict__ metric, uint8_t* __restrict__ cw,
+    void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
+    int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves, int32_t* __restrict__ stats)
 {
+    const int PP = KP / 16;  // pieces per path (4, 8 or 16: a path's pieces share a wave)
     const int NB = N / 8;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < F * L;
-         idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t total = F * L * PP;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        hdr[2] = hdr[0] * L;
+        if (stats) atomicAdd(&stats[0], hdr[0]);
+    }
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ((total + 63) & ~int64_t(63));
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const bool live = g < total;
+        const int64_t idx = live ? g / PP : 0;
+        const int piece = (int)(g % PP);
+        const int j0 = 16 * piece;
         const int64_t f = idx / L;
         const int k = (int)(idx % L);
-        const uint8_t* a = anchors + (size_t)idx * NB;
-        if (out_moves)
-            for (int t = 0; t < T; ++t) out_moves[(size_t)idx * T + t] = -1;
-        const int s = slot[f];
+        const bool inpos = live && j0 < N;
+        const uint32_t bits = inpos ? *(const uint16_t*)(anchors + (size_t)idx * NB + 2 * piece) : 0u;
+        const int s = live ? slot[f] : -1;
+        int part = 0;
+        if (!FLOAT && inpos) {
+            const int8_t* q = (const int8_t*)llr + (size_t)f * N + j0;
+            v4i qv = *(const v4i*)q;
+            v4i zv;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                uint32_t wq = (uint32_t)qv[d], wz = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int v = (int8_t)(wq >> (8 * b));
+                    const int bit = (bits >> (4 * d + b)) & 1;
+                    part += bit ? v : 0;
+                    wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
+                }
+                zv[d] = (int)wz;
+            }
+            if (s >= 0) *(v4i*)((int8_t*)zbuf + (size_t)((int64_t)s * L + k) * KP + j0) = zv;
+        } else if (!FLOAT && live && s >= 0) {
+            *(v4i*)((int8_t*)zbuf + (size_t)((int64_t)s * L + k) * KP + j0) = v4i{0, 0, 0, 0};
+        }
+        if (FLOAT && inpos && s >= 0) {
+            const float* y = (const float*)llr + (size_t)f * N + j0;
+            float* z = (float*)zbuf + (size_t)((int64_t)s * L + k) * N + j0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) z[j] = ((bits >> j) & 1) ? -y[j] : y[j];
+        }
+        // sum the pieces of this path (consecutive lanes)
+        for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
+        if (!live) continue;
         if (s < 0) {
-            if (k != 0) continue;
-            for (int b = 0; b < NB; ++b) out_cw[(size_t)f * NB + b] = a[b];
-            if (out_k) out_k[f] = 0;
-            if (out_metric) {
-                if (FLOAT) {
-                    const float* y = (const float*)llr + (size_t)f * N;
-                    float e = 0.0f;
-                    for (int j = 0; j < N; ++j) {
-                        const float x = ((a[j >> 3] >> (j & 7)) & 1) ? -1.0f : 1.0f;
-                        const float dlt = __fsub_rn(y[j], x);
-                        e = __fadd_rn(e, __fmul_rn(dlt, dlt));
+            if (k != 0) goto moves_fill;
+            if (inpos) *(uint16_t*)(out_cw + (size_t)f * NB + 2 * piece) = (uint16_t)bits;
+            if (piece == 0) {
+                if (out_k) out_k[f] = 0;
+                if (out_metric) {
+                    if (FLOAT) {
+                        const uint8_t* a = anchors + (size_t)idx * NB;
+                        const float* y = (const float*)llr + (size_t)f * N;
+                        float e = 0.0f;
+                        for (int j = 0; j < N; ++j) {
+                            const float x = ((a[j >> 3] >> (j & 7)) & 1) ? -1.0f : 1.0f;
+                            const float dlt = __fsub_rn(y[j], x);
+                            e = __fadd_rn(e, __fmul_rn(dlt, dlt));
+                        }
+                        out_metric[f] = (int32_t)__float_as_uint(e);
+                    } else {
+                        out_metric[f] = part;
                     }
-                    out_metric[f] = (int32_t)__float_as_uint(e);
-                } else {
-                    const int8_t* q = (const int8_t*)llr + (size_t)f * N;
-                    int e = 0;
-                    for (int j = 0; j < N; ++j) e += ((a[j >> 3] >> (j & 7)) & 1) ? q[j] : 0;
-                    out_metric[f] = e;
                 }
             }
-            continue;
-        }
-        const int64_t col = (int64_t)s * L + k;
-        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = a[b];
-        act0[col] = (int32_t)col;
-        if (FLOAT) {
-            const float* y = (const float*)llr + (size_t)f * N;
-            float* z = (float*)zbuf + (size_t)col * N;
-            for (int j = 0; j < N; ++j) z[j] = ((a[j >> 3] >> (j & 7)) & 1) ? -y[j] : y[j];
-            key64[col] = ~0ull;
         } else {
-            const int8_t* q = (const int8_t*)llr + (size_t)f * N;
-            int8_t* z = (int8_t*)zbuf + (size_t)col * KP;
-            int e = 0;
-            for (int j = 0; j < KP; ++j) {
-                const int bit = j < N ? (a[j >> 3] >> (j & 7)) & 1 : 0;
-                const int v = j < N ? q[j] : 0;
-                z[j] = (int8_t)(bit ? -v : v);
-                e += bit ? v : 0;
+            const int64_t col = (int64_t)s * L + k;
+            if (inpos) *(uint16_t*)(cw + (size_t)col * NB + 2 * piece) = (uint16_t)bits;
+            if (piece == 0) {
+                act0[col] = (int32_t)col;
+                key64[col] = FLOAT ? ~0ull : (uint64_t)LLONG_MAX;
+                if (!FLOAT) metric[col] = part;
             }
-            metric[col] = e;
-            key32[col] = INT_MAX;
         }
+    moves_fill:
+        if (out_moves)
+            for (int t = piece; t < T; t += PP) out_moves[(size_t)idx * T + t] = -1;
     }
 }
 
 // ---------------------------------------------------------------- int8 search
-// Unpack 32 bits (LSB first) into 32 bytes of 0/1: every nibble spreads to a
-// dword with one multiply (the four shifted copies do not overlap).
+// Unpack 32 bits (LSB first) into 32 bytes: a set bit becomes 0x80 (-128),
+// a clear bit 0.  Every nibble spreads to bit 7 of four bytes with one
+// multiply (the four shifted copies of the nibble do not overlap).
 __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
 {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (((x >> (4 * k)) & 0xFu) * 0x00204081u) & 0x01010101u;
+    for (int k = 0; k < 8; ++k) o[k] = (((x >> (4 * k)) & 0xFu) * 0x10204080u) & 0x80808080u;
 }
 
 template <int KP, int NC, int NWAVES>
 __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
     const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int N, int64_t P,
-    const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, int32_t* __restrict__ keys)
+    const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, long long* __restrict__ keys)
 {
     constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
     constexpr int CT = NWAVES * 16 * NC;        // columns per tile
@@ -316,9 +338,9 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
                     zf[c][h] = v4i{0, 0, 0, 0};
             }
         }
-        int best[NC];
+        long long best[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) best[c] = INT_MAX;
+        for (int c = 0; c < NC; ++c) best[c] = LLONG_MAX;
 
         uint32_t reg[UR];
         fetch(c0, reg);
@@ -336,9 +358,13 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
                 const int8_t* src = &lds[b][(tt * 16 + li) * RS + lg * (KP / 4)];
 #pragma unroll
                 for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
+                // accumulator seed: the row's index within the chunk, so that
+                // D = 128 S + row orders by (S, row)
+                const int r0 = tt * 16 + lg * 4;
+                const v4i seed = {r0, r0 + 1, r0 + 2, r0 + 3};
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
-                    v4i acc = {0, 0, 0, 0};
+                    v4i acc = seed;
 #pragma unroll
                     for (int h = 0; h < HK; ++h) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc, 0, 0, 0);
                     cm[c] = min(cm[c], min(acc[0], acc[1]));
@@ -346,89 +372,82 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
                 }
             }
 #pragma unroll
-            for (int c = 0; c < NC; ++c) best[c] = min(best[c], (cm[c] << 16) | k);
+            for (int c = 0; c < NC; ++c) {
+                // (S, p) with p = 128 k + row: S = floor(D / 128), row = D mod 128
+                const long long key = ((long long)(cm[c] >> 7) << 32) | (long long)(uint32_t)((k << 7) | (cm[c] & 127));
+                best[c] = key < best[c] ? key : best[c];
+            }
             if (k + 1 < c1) store(b ^ 1, reg);
             __syncthreads();
         }
         // lanes li, li+16, li+32, li+48 hold the same column
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            int v = best[c];
-            v = min(v, __shfl_xor(v, 16));
-            v = min(v, __shfl_xor(v, 32));
+            long long v = best[c];
+            long long o = __shfl_xor(v, 16);
+            v = o < v ? o : v;
+            o = __shfl_xor(v, 32);
+            v = o < v ? o : v;
             if (lg == 0 && colid[c] >= 0) atomicMin(&keys[colid[c]], v);
         }
     }
 }
 
 // ---------------------------------------------------------------- int8 resolve
-// One wave per active column: decode (S_min, chunk), rescore the chunk's 128
-// moves exactly, take the first move attaining S_min, apply it.
+// Thread per active column: the search left the exact (S_min, p*) in the key;
+// apply the move when S_min < 0 (flip the centre bits and the signs of the
+// stored -z on the move's support, update M, log p*) and append the column
+// to the next active list with one atomic per wave.
 __global__ __launch_bounds__(256) void resolve_i8_kernel(
     int8_t* __restrict__ z, uint8_t* __restrict__ cw, int32_t* __restrict__ metric, const uint8_t* __restrict__ moves,
     int N, int KP, int64_t P, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
-    int32_t* __restrict__ hdr, int t, int T, int32_t* __restrict__ keys, const int32_t* __restrict__ fid, int L,
+    int32_t* __restrict__ hdr, int t, int T, long long* __restrict__ keys, const int32_t* __restrict__ fid, int L,
     int32_t* __restrict__ out_moves)
 {
-    __shared__ int8_t zs[4][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
     const int n = hdr[2 + t];
-    const int NB = N / 8;
-    const int nwaves = gridDim.x * 4;
-    for (int pos = blockIdx.x * 4 + w; pos < n; pos += nwaves) {
-        const int col = act_in[pos];
-        int key = 0;
-        if (lane == 0) {
-            key = keys[col];
-            keys[col] = INT_MAX;  // ready for the next iteration
-        }
-        key = __shfl(key, 0);
-        const int S = key >> 16;
-        const int chunk = key & 0xFFFF;
-        if (key == INT_MAX || S >= 0) continue;  // no improving move: the path stops
-        int8_t* zc = z + (size_t)col * KP;
-        for (int j = lane; j < N; j += 64) zs[w][j] = zc[j];
-        __builtin_amdgcn_wave_barrier();
-        int sc[2];
-#pragma unroll
-        for (int hlf = 0; hlf < 2; ++hlf) {
-            const int64_t p = (int64_t)chunk * RC + hlf * 64 + lane;
-            int s = INT_MAX;
-            if (p < P) {
-                s = 0;
-                const uint8_t* row = moves + (size_t)p * NB;
-                for (int wd = 0; wd < N / 32; ++wd) {
-                    uint32_t bits = *(const uint32_t*)(row + 4 * wd);
-                    while (bits) {
-                        const int j = 32 * wd + __builtin_ctz(bits);
-                        s += zs[w][j];
-                        bits &= bits - 1;
+    const int NB = N / 8, NWD = N / 32;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int pos = base + lane;
+        bool moved = false;
+        int col = 0;
+        if (pos < n) {
+            col = act_in[pos];
+            const long long key = keys[col];
+            keys[col] = LLONG_MAX;  // ready for the next iteration
+            const int S = (int)(key >> 32);
+            const int64_t p = (int64_t)(uint32_t)key;
+            if (key != LLONG_MAX && S < 0) {
+                if (p >= P) {
+                    atomicAdd(&hdr[1], 1);
+                } else {
+                    const uint32_t* mv = (const uint32_t*)(moves + (size_t)p * NB);
+                    uint32_t* c32 = (uint32_t*)(cw + (size_t)col * NB);
+                    int8_t* zc = z + (size_t)col * KP;
+                    for (int wd = 0; wd < NWD; ++wd) {
+                        uint32_t bits = mv[wd];
+                        c32[wd] ^= bits;
+                        while (bits) {
+                            const int j = 32 * wd + __builtin_ctz(bits);
+                            zc[j] = (int8_t)(-zc[j]);
+                            bits &= bits - 1;
+                        }
                     }
+                    metric[col] += S;
+                    if (out_moves) {
+                        const int s = col / L, k = col % L;
+                        out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)p;
+                    }
+                    moved = true;
                 }
             }
-            sc[hlf] = s;
         }
-        const uint64_t b0 = __ballot(sc[0] == S), b1 = __ballot(sc[1] == S);
-        int64_t pstar = -1;
-        if (b0) pstar = (int64_t)chunk * RC + __builtin_ctzll(b0);
-        else if (b1) pstar = (int64_t)chunk * RC + 64 + __builtin_ctzll(b1);
-        if (pstar < 0) {
-            if (lane == 0) atomicAdd(&hdr[1], 1);
-            continue;
-        }
-        const uint8_t* mv = moves + (size_t)pstar * NB;
-        for (int j = lane; j < N; j += 64)
-            if ((mv[j >> 3] >> (j & 7)) & 1) zc[j] = (int8_t)(-zs[w][j]);
-        for (int bb = lane; bb < NB; bb += 64) cw[(size_t)col * NB + bb] ^= mv[bb];
-        if (lane == 0) {
-            metric[col] += S;
-            if (out_moves) {
-                const int s = col / L, k = col % L;
-                out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)pstar;
-            }
-            const int o = atomicAdd(&hdr[2 + t + 1], 1);
-            act_out[o] = col;
-        }
+        const uint64_t bal = __ballot(moved);
+        int wbase = 0;
+        if (lane == 0 && bal) wbase = atomicAdd(&hdr[2 + t + 1], __popcll(bal));
+        wbase = __shfl(wbase, 0);
+        if (moved) act_out[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = col;
     }
 }
 
@@ -509,28 +528,50 @@ __global__ __launch_bounds__(256) void resolve_f32_kernel(
     const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out, int32_t* __restrict__ hdr, int t, int T,
     unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves)
 {
-    const int NB = N / 8;
+    const int lane = threadIdx.x & 63;
+    const int NB = N / 8, NWD = N / 32;
     const int n = hdr[2 + t];
-    for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < n; pos += gridDim.x * blockDim.x) {
-        const int col = act_in[pos];
-        const unsigned long long key = keys[col];
-        keys[col] = ~0ull;
-        const uint32_t ob = (uint32_t)(key >> 32);
-        // orderable(S) < orderable(+0) <=> S < 0
-        if (key == ~0ull || ob >= 0x80000000u) continue;
-        const int64_t p = (int64_t)(key & 0xFFFFFFFFull);
-        if (p >= P) { atomicAdd(&hdr[1], 1); continue; }
-        const uint8_t* mv = moves + (size_t)p * NB;
-        float* zc = z + (size_t)col * N;
-        for (int j = 0; j < N; ++j)
-            if ((mv[j >> 3] >> (j & 7)) & 1) zc[j] = -zc[j];
-        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] ^= mv[b];
-        if (out_moves) {
-            const int s = col / L, k = col % L;
-            out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)p;
+    const int stride = gridDim.x * blockDim.x;
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
+        const int pos = base + lane;
+        bool moved = false;
+        int col = 0;
+        if (pos < n) {
+            col = act_in[pos];
+            const unsigned long long key = keys[col];
+            keys[col] = ~0ull;
+            const uint32_t ob = (uint32_t)(key >> 32);
+            // orderable(S) < orderable(+0) = 0x80000000 <=> S < 0
+            if (key != ~0ull && ob < 0x80000000u) {
+                const int64_t p = (int64_t)(key & 0xFFFFFFFFull);
+                if (p >= P) {
+                    atomicAdd(&hdr[1], 1);
+                } else {
+                    const uint32_t* mv = (const uint32_t*)(moves + (size_t)p * NB);
+                    uint32_t* c32 = (uint32_t*)(cw + (size_t)col * NB);
+                    float* zc = z + (size_t)col * N;
+                    for (int wd = 0; wd < NWD; ++wd) {
+                        uint32_t bits = mv[wd];
+                        c32[wd] ^= bits;
+                        while (bits) {
+                            const int j = 32 * wd + __builtin_ctz(bits);
+                            zc[j] = -zc[j];
+                            bits &= bits - 1;
+                        }
+                    }
+                    if (out_moves) {
+                        const int s = col / L, k = col % L;
+                        out_moves[((size_t)fid[s] * L + k) * T + t] = (int32_t)p;
+                    }
+                    moved = true;
+                }
+            }
         }
-        const int o = atomicAdd(&hdr[2 + t + 1], 1);
-        act_out[o] = col;
+        const uint64_t bal = __ballot(moved);
+        int wbase = 0;
+        if (lane == 0 && bal) wbase = atomicAdd(&hdr[2 + t + 1], __popcll(bal));
+        wbase = __shfl(wbase, 0);
+        if (moved) act_out[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = col;
     }
 }
 
@@ -584,7 +625,7 @@ void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_
     const int N = 1 << sg.m;
     constexpr int NC = 8, NW = 4;
     hipLaunchKernelGGL((search_i8_kernel<KP, NC, NW>), dim3(grid), dim3(NW * WAVE), 0, s, (const int8_t*)w.z,
-                       sg.moves, N, sg.P, w.act[t & 1], w.hdr, t, w.key32);
+                       sg.moves, N, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
 }
 
 void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
@@ -606,20 +647,22 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
     const int N = 1 << sg.m, KP = kpad(N);
     const bool fl = sg.dtype == MPWSD_F32;
     const int cus = device_cus();
-    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, sg.crc_ok, sg.F, L, T, w.hdr, w.fid, w.slot, stats);
+    hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(64), 0, s, w.hdr, 4 + T);
+    hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((sg.F + 255) / 256)), dim3(256), 0, s, sg.crc_ok, sg.F, w.hdr,
+                       w.fid, w.slot);
     {
-        const int64_t work = sg.F * L;
+        const int64_t work = sg.F * L * (KP / 16);
         const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
         if (fl)
-            hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.crc_ok, sg.F, L,
-                               T, N, KP, w.slot, w.act[0], w.key32, w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
-                               sg.out_metric, sg.out_moves);
+            hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
+                               w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                               sg.out_metric, sg.out_moves, stats);
         else
-            hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.crc_ok, sg.F,
-                               L, T, N, KP, w.slot, w.act[0], w.key32, w.key64, w.metric, w.cw, w.z, sg.out_cw,
-                               sg.out_k, sg.out_metric, sg.out_moves);
+            hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N,
+                               KP, w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw,
+                               sg.out_k, sg.out_metric, sg.out_moves, stats);
     }
-    const int resolve_blocks = cus * 8;
+    const int resolve_blocks = cus * 4;
     for (int t = 0; t < T; ++t) {
         if (ev) (void)hipEventRecord(ev[2 * t], s);
         if (fl) {
@@ -636,7 +679,7 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
             }
             if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
             hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
-                               sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, w.key32, w.fid,
+                               sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (long long*)w.key64, w.fid,
                                L, sg.out_moves);
         }
     }
