@@ -247,19 +247,24 @@ __global__ __launch_bounds__(256) void init_kernel(
 
 // ---------------------------------------------------------------- int8 search
 // Unpack 32 bits (LSB first) into 32 bytes: a set bit becomes 0x80 (-128),
-// a clear bit 0.  Every nibble spreads to bit 7 of four bytes with one
-// multiply (the four shifted copies of the nibble do not overlap).
+// a clear bit 0.  Each nibble, placed at bits 7..10, spreads to bit 7 of four
+// bytes with one full-rate 24-bit multiply by 1 + 2^7 + 2^14 + 2^21 (the four
+// shifted copies do not overlap).
 __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
 {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = (((x >> (4 * k)) & 0xFu) * 0x10204080u) & 0x80808080u;
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t t7 = (k < 2 ? (x << (7 - 4 * k)) : (x >> (4 * k - 7))) & 0x780u;
+        o[k] = __umul24(t7, 0x204081u) & 0x80808080u;
+    }
 }
 
-template <int KP, int NC, int NWAVES>
+template <int N, int NC, int NWAVES>
 __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
-    const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int N, int64_t P,
+    const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
     const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, long long* __restrict__ keys)
 {
+    constexpr int KP = N < 64 ? 64 : N;         // K padded to the MFMA depth
     constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
     constexpr int CT = NWAVES * 16 * NC;        // columns per tile
     constexpr int HK = KP / 64;                 // MFMAs per 16 x 16 output tile
@@ -268,8 +273,8 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
 
     const int n = hdr[2 + t];
     if (n <= 0) return;
-    const int NB = N / 8;                       // packed bytes per move
-    const int UW = N / 32;                      // 32-bit units per move
+    constexpr int NB = N / 8;                   // packed bytes per move
+    constexpr int UW = N / 32;                  // 32-bit units per move
     const int tiles = (n + CT - 1) / CT;
     const int C = (int)((P + RC - 1) / RC);
     const int64_t U = (int64_t)tiles * C;
@@ -279,6 +284,7 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
+    const v4i seed0 = {4 * lg, 4 * lg + 1, 4 * lg + 2, 4 * lg + 3};
 
     if (N < KP) {  // positions >= N stay zero for the whole launch
         for (int e = tid; e < 2 * RC; e += NT) {
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
 
     // this thread's share of a chunk: units of 32 packed bits
     constexpr int UR = (RC * KP / 32 + NT - 1) / NT;
-    const int units = RC * UW;
+    constexpr int units = RC * UW;
     auto fetch = [&](int chunk, uint32_t (&reg)[UR]) {
 #pragma unroll
         for (int r = 0; r < UR; ++r) {
@@ -338,17 +344,20 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
                     zf[c][h] = v4i{0, 0, 0, 0};
             }
         }
-        long long best[NC];
+        // Chunks are swept in decreasing order, so a chunk replaces the
+        // running best when its minimum S is <= the best S (ties go to the
+        // lower chunk); within a chunk D = 128 S + row orders by (S, row).
+        int run[NC], runk[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) best[c] = LLONG_MAX;
+        for (int c = 0; c < NC; ++c) { run[c] = INT_MAX; runk[c] = 0; }
 
         uint32_t reg[UR];
-        fetch(c0, reg);
+        fetch(c1 - 1, reg);
         store(0, reg);
         __syncthreads();
-        for (int k = c0; k < c1; ++k) {
-            const int b = (k - c0) & 1;
-            if (k + 1 < c1) fetch(k + 1, reg);
+        for (int k = c1 - 1; k >= c0; --k) {
+            const int b = (c1 - 1 - k) & 1;
+            if (k > c0) fetch(k - 1, reg);
             int cm[NC];
 #pragma unroll
             for (int c = 0; c < NC; ++c) cm[c] = INT_MAX;
@@ -358,28 +367,36 @@ __global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
                 const int8_t* src = &lds[b][(tt * 16 + li) * RS + lg * (KP / 4)];
 #pragma unroll
                 for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
-                // accumulator seed: the row's index within the chunk, so that
-                // D = 128 S + row orders by (S, row)
-                const int r0 = tt * 16 + lg * 4;
-                const v4i seed = {r0, r0 + 1, r0 + 2, r0 + 3};
+                // accumulator seed: the row's index within the chunk
+                const v4i seed = seed0 + v4i{16 * tt, 16 * tt, 16 * tt, 16 * tt};
+                // all column blocks' MFMAs back to back into separate
+                // accumulators, so the matrix pipe never waits on the epilogue
+                v4i acc[NC];
 #pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    v4i acc = seed;
+                for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[0], zf[c][0], seed, 0, 0, 0);
 #pragma unroll
-                    for (int h = 0; h < HK; ++h) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc, 0, 0, 0);
-                    cm[c] = min(cm[c], min(acc[0], acc[1]));
-                    cm[c] = min(cm[c], min(acc[2], acc[3]));
+                for (int h = 1; h < HK; ++h)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc[c], 0, 0, 0);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {  // two v_min3 per four values
+                    const int t3 = min(min(acc[c][0], acc[c][1]), acc[c][2]);
+                    cm[c] = min(min(cm[c], t3), acc[c][3]);
                 }
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                // (S, p) with p = 128 k + row: S = floor(D / 128), row = D mod 128
-                const long long key = ((long long)(cm[c] >> 7) << 32) | (long long)(uint32_t)((k << 7) | (cm[c] & 127));
-                best[c] = key < best[c] ? key : best[c];
+                const bool take = cm[c] <= (run[c] | 127);  // S(cm) <= S(run)
+                run[c] = take ? cm[c] : run[c];
+                runk[c] = take ? k : runk[c];
             }
-            if (k + 1 < c1) store(b ^ 1, reg);
+            if (k > c0) store(b ^ 1, reg);
             __syncthreads();
         }
+        long long best[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            best[c] = ((long long)(run[c] >> 7) << 32) | (long long)(uint32_t)((runk[c] << 7) | (run[c] & 127));
         // lanes li, li+16, li+32, li+48 hold the same column
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -619,13 +636,12 @@ __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __res
 }
 
 // ---------------------------------------------------------------- launches
-template <int KP>
+template <int N>
 void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
 {
-    const int N = 1 << sg.m;
     constexpr int NC = 8, NW = 4;
-    hipLaunchKernelGGL((search_i8_kernel<KP, NC, NW>), dim3(grid), dim3(NW * WAVE), 0, s, (const int8_t*)w.z,
-                       sg.moves, N, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
+    hipLaunchKernelGGL((search_i8_kernel<N, NC, NW>), dim3(grid), dim3(NW * WAVE), 0, s, (const int8_t*)w.z,
+                       sg.moves, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
 }
 
 void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
@@ -672,7 +688,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
                                N, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
                                (unsigned long long*)w.key64, w.fid, L, sg.out_moves);
         } else {
-            switch (KP) {
+            switch (N) {
+            case 32: launch_search_i8<32>(w, sg, t, s, cus * 2); break;
             case 64: launch_search_i8<64>(w, sg, t, s, cus * 2); break;
             case 128: launch_search_i8<128>(w, sg, t, s, cus * 2); break;
             default: launch_search_i8<256>(w, sg, t, s, cus * 2); break;
