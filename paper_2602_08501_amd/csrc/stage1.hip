@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.h"
 
@@ -62,6 +63,21 @@ template <int NW> __device__ inline void polar_bits(uint32_t (&w)[NW], int lev)
     }
 }
 
+// Schedule of the successive-cancellation tree: entry i (a leaf index) is 0
+// for an ordinary leaf, or (kind << 4 | level) when a special subtree of
+// 2^level leaves starts at leaf i: kind 1 = all frozen (rate 0), kind 2 = all
+// frozen but the last leaf (repetition).  With min-sum updates the path
+// metric a subtree adds for a decided sub-codeword equals that codeword's
+// discrepancy against the subtree's LLRs, so such a subtree is settled from
+// its LLRs alone: rate 0 adds D0 = sum_{l<0} |l|, a repetition node offers
+// the children PM + D0 (bit 0) and PM + D1, D1 = sum_{l>0} l.  In integer
+// arithmetic this is exactly the leaf-by-leaf result; the float form keeps
+// the leaf-by-leaf order of additions (all entries 0).
+struct Sched {
+    uint8_t v[256];
+};
+constexpr int KIND_R0 = 1, KIND_REP = 2;
+
 template <int M, int L, bool FLOAT> struct Scl {
     using A = Arith<FLOAT>;
     using V = typename A::V;
@@ -69,11 +85,12 @@ template <int M, int L, bool FLOAT> struct Scl {
     static constexpr int N = 1 << M;
     static constexpr int NW = N / 32;    // words of decided bits per path
     static constexpr int G = WAVE / L;   // frames per wave
+    using Key = typename std::conditional<FLOAT, uint64_t, uint32_t>::type;
 
     struct Smem {
         S buf[(N - 1) * WAVE];  // level l of lane x: rows [2^l - 1, 2^(l+1) - 1), column x
         S ch[G * N];            // channel LLRs of the wave's frames
-        uint64_t key[2 * WAVE];
+        alignas(16) Key key[2 * WAVE];
         int sel[WAVE];
         V cpm[WAVE];
         int cvalid[WAVE];
@@ -83,9 +100,11 @@ template <int M, int L, bool FLOAT> struct Scl {
 
     // Recompute level LEV of this lane's path from level LEV + 1 (the
     // channel when LEV = M - 1): f for a left child, g for a right child with
-    // the left sibling's bits re-encoded.
+    // the left sibling's bits re-encoded.  When sums is set, also returns
+    // D0 = sum of |l| over negative outputs and D1 = sum of positive outputs.
     template <int LEV>
-    __device__ static V level(Smem& sm, int lane, int gbase, int i, bool use_g, uint64_t ptrs, const uint32_t (&ub)[NW])
+    __device__ static V level(Smem& sm, int lane, int gbase, int i, bool use_g, bool sums, uint64_t ptrs,
+                              const uint32_t (&ub)[NW], V& d0, V& d1)
     {
         constexpr int n = 1 << LEV;
         constexpr int PW = (n + 31) / 32;
@@ -111,7 +130,7 @@ template <int M, int L, bool FLOAT> struct Scl {
             stride = WAVE;
         }
         S* out = sm.buf + (n - 1) * WAVE + lane;
-        V o = 0;
+        V o = 0, s0 = 0, s1 = 0;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
             const V a = (V)par[k * stride];
@@ -119,44 +138,55 @@ template <int M, int L, bool FLOAT> struct Scl {
             if (use_g) o = ((ps[k >> 5] >> (k & 31)) & 1u) ? (V)(b - a) : (V)(b + a);
             else o = f_minsum(a, b);
             out[k * WAVE] = (S)o;
+            if (!FLOAT && sums) {
+                s0 += o < 0 ? (V)-o : (V)0;
+                s1 += o > 0 ? o : (V)0;
+            }
         }
+        d0 = s0;
+        d1 = s1;
         return o;
     }
 
+    // Levels D, D-1, ..., stop for the node starting at leaf i: level D is a
+    // right child (g) unless i = 0; the levels below are left children (f).
     template <int D>
-    __device__ static V run(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
+    __device__ static V run(Smem& sm, int lane, int gbase, int i, int stop, int slot, uint64_t& ptrs,
+                            const uint32_t (&ub)[NW], bool first, V& d0, V& d1)
     {
-        V lam = level<D>(sm, lane, gbase, i, i > 0, ptrs, ub);
+        V lam = level<D>(sm, lane, gbase, i, first && i > 0, D == stop, ptrs, ub, d0, d1);
         ptrs = (ptrs & ~(0xFFull << (8 * D))) | ((uint64_t)slot << (8 * D));
         __builtin_amdgcn_wave_barrier();
         if constexpr (D > 0) {
-            lam = run_f<D - 1>(sm, lane, gbase, i, slot, ptrs, ub);
+            if (D > stop) lam = run<D - 1>(sm, lane, gbase, i, stop, slot, ptrs, ub, false, d0, d1);
         }
         return lam;
     }
 
-    template <int D>
-    __device__ static V run_f(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
-    {
-        V lam = level<D>(sm, lane, gbase, i, false, ptrs, ub);
-        ptrs = (ptrs & ~(0xFFull << (8 * D))) | ((uint64_t)slot << (8 * D));
-        __builtin_amdgcn_wave_barrier();
-        if constexpr (D > 0) lam = run_f<D - 1>(sm, lane, gbase, i, slot, ptrs, ub);
-        return lam;
-    }
-
-    __device__ static V leaf(Smem& sm, int lane, int gbase, int i, int slot, uint64_t& ptrs, const uint32_t (&ub)[NW])
+    __device__ static V node(Smem& sm, int lane, int gbase, int i, int stop, int slot, uint64_t& ptrs,
+                             const uint32_t (&ub)[NW], V& d0, V& d1)
     {
         const int d = (i == 0) ? M - 1 : __builtin_ctz(i);
         switch (d) {
-        case 0: return run<0>(sm, lane, gbase, i, slot, ptrs, ub);
-        case 1: return run<1>(sm, lane, gbase, i, slot, ptrs, ub);
-        case 2: return run<2>(sm, lane, gbase, i, slot, ptrs, ub);
-        case 3: return run<3>(sm, lane, gbase, i, slot, ptrs, ub);
-        case 4: return run<4>(sm, lane, gbase, i, slot, ptrs, ub);
-        case 5: if constexpr (M > 5) return run<5>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
-        case 6: if constexpr (M > 6) return run<6>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
-        default: if constexpr (M > 7) return run<7>(sm, lane, gbase, i, slot, ptrs, ub); else return 0;
+        case 0: return run<0>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1);
+        case 1: return run<1>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1);
+        case 2: return run<2>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1);
+        case 3: return run<3>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1);
+        case 4: return run<4>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1);
+        case 5: if constexpr (M > 5) return run<5>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1); else return 0;
+        case 6: if constexpr (M > 6) return run<6>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1); else return 0;
+        default: if constexpr (M > 7) return run<7>(sm, lane, gbase, i, stop, slot, ptrs, ub, true, d0, d1); else return 0;
+        }
+    }
+
+    __device__ static Key make_key(bool valid, V pm, int idx)
+    {
+        if constexpr (FLOAT) {
+            const uint64_t hi = valid ? (uint64_t)A::key_bits(pm) : 0xFFFFFFFFull;
+            return (hi << 8) | (uint64_t)idx;
+        } else {
+            // |PM| <= 127 N < 2^15: (PM, index) in one 32-bit key
+            return ((valid ? (uint32_t)pm : 0x7FFFFFu) << 7) | (uint32_t)idx;
         }
     }
 };
@@ -164,7 +194,7 @@ template <int M, int L, bool FLOAT> struct Scl {
 template <int M, int L, bool FLOAT>
 __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F,
                                                    uint64_t info0, uint64_t info1, uint64_t info2, uint64_t info3,
-                                                   int crc_len, uint32_t crc_poly,
+                                                   int crc_len, uint32_t crc_poly, Sched sched,
                                                    uint8_t* __restrict__ anchors, uint8_t* __restrict__ crc_ok,
                                                    int32_t* __restrict__ pm_out)
 {
@@ -172,6 +202,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     using A = typename K::A;
     using V = typename K::V;
     using S = typename K::S;
+    using Key = typename K::Key;
     constexpr int N = K::N, NW = K::NW, G = K::G;
     __shared__ typename K::Smem sm;
 
@@ -198,36 +229,51 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
 #pragma unroll
     for (int l = 0; l < M; ++l) ptrs |= (uint64_t)slot << (8 * l);
 
-    for (int i = 0; i < N; ++i) {
-        const V lam = K::leaf(sm, lane, gbase, i, slot, ptrs, ub);
-        const bool frozen = ((info[i >> 6] >> (i & 63)) & 1ull) == 0;
-        const V mag = lam < 0 ? -lam : lam;
-        const int hd = lam < 0 ? 1 : 0;
+    for (int i = 0; i < N;) {
+        const int e = FLOAT ? 0 : sched.v[i];
+        const int lev = e & 15, kind = e >> 4;
+        V d0, d1;
+        const V lam = K::node(sm, lane, gbase, i, lev, slot, ptrs, ub, d0, d1);
+        const int last = i + (1 << lev) - 1;  // the leaf a decision is taken at
+        i += 1 << lev;
+        if (kind == 0) {
+            d0 = lam < 0 ? (V)-lam : (V)0;
+            d1 = lam > 0 ? lam : (V)0;
+        }
+        const bool frozen = kind == KIND_R0 || (kind == 0 && ((info[last >> 6] >> (last & 63)) & 1ull) == 0);
         if (frozen) {
-            if (valid && hd) pm = pm + mag;
-            continue;  // u_i = 0 already
+            if (valid) pm = pm + d0;
+            continue;  // u = 0 already
         }
         // information bit: rank the 2L children by (PM, parent slot, bit)
         V cp[2];
-        cp[0] = (hd == 0) ? pm : (V)(pm + mag);
-        cp[1] = (hd == 1) ? pm : (V)(pm + mag);
-        uint64_t key[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const uint64_t hi = valid ? (uint64_t)A::key_bits(cp[u]) : 0xFFFFFFFFull;
-            key[u] = (hi << 8) | (uint64_t)(2 * slot + u);
-            sm.key[2 * lane + u] = key[u];
-        }
+        cp[0] = (V)(pm + d0);
+        cp[1] = (V)(pm + d1);
+        Key key[2];
+        key[0] = K::make_key(valid, cp[0], 2 * slot);
+        key[1] = K::make_key(valid, cp[1], 2 * slot + 1);
+        sm.key[2 * lane] = key[0];
+        sm.key[2 * lane + 1] = key[1];
         sm.ptr[lane] = ptrs;
 #pragma unroll
         for (int w = 0; w < NW; ++w) sm.ub[w * WAVE + lane] = ub[w];
         __syncthreads();
         int rank0 = 0, rank1 = 0;
+        if constexpr (!FLOAT && L >= 2) {
+            const uint4* kv = (const uint4*)&sm.key[2 * gbase];
 #pragma unroll
-        for (int c = 0; c < 2 * L; ++c) {
-            const uint64_t o = sm.key[2 * gbase + c];
-            rank0 += o < key[0];
-            rank1 += o < key[1];
+            for (int c = 0; c < 2 * L / 4; ++c) {
+                const uint4 o = kv[c];
+                rank0 += (o.x < key[0]) + (o.y < key[0]) + (o.z < key[0]) + (o.w < key[0]);
+                rank1 += (o.x < key[1]) + (o.y < key[1]) + (o.z < key[1]) + (o.w < key[1]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 2 * L; ++c) {
+                const Key o = sm.key[2 * gbase + c];
+                rank0 += o < key[0];
+                rank1 += o < key[1];
+            }
         }
         if (rank0 < L) {
             sm.sel[gbase + rank0] = 2 * slot;
@@ -247,17 +293,18 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
         ptrs = sm.ptr[par];
 #pragma unroll
         for (int w = 0; w < NW; ++w) ub[w] = sm.ub[w * WAVE + par];
-        ub[i >> 5] |= (uint32_t)(c & 1) << (i & 31);
+        ub[last >> 5] |= (uint32_t)(c & 1) << (last & 31);
         __syncthreads();
     }
 
     // final order: (PM, slot) ascending
     const uint64_t fkey = ((uint64_t)(valid ? A::key_bits(pm) : 0xFFFFFFFFu) << 8) | (uint64_t)slot;
-    sm.key[lane] = fkey;
+    uint64_t* fk = (uint64_t*)sm.ptr;
+    fk[lane] = fkey;
     __syncthreads();
     int rank = 0;
 #pragma unroll
-    for (int c = 0; c < L; ++c) rank += sm.key[gbase + c] < fkey;
+    for (int c = 0; c < L; ++c) rank += fk[gbase + c] < fkey;
     uint32_t cw[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) cw[w] = ub[w];
@@ -302,6 +349,33 @@ __global__ void quantize_kernel(const float* __restrict__ y, int64_t n, float s,
     }
 }
 
+// Maximal rate-0 and repetition subtrees of the frozen pattern, in SC order.
+Sched make_sched(int m, const uint64_t* info)
+{
+    Sched sc{};
+    const int n = 1 << m;
+    auto is_info = [&](int j) { return ((info[j >> 6] >> (j & 63)) & 1ull) != 0; };
+    struct Rec {
+        static void visit(Sched& sc, const decltype(is_info)& inf, int lev, int a)
+        {
+            const int n = 1 << lev;
+            if (lev > 0) {
+                int cnt = 0;
+                for (int j = a; j < a + n; ++j) cnt += inf(j);
+                if (cnt == 0) { sc.v[a] = (uint8_t)((KIND_R0 << 4) | lev); return; }
+                if (cnt == 1 && inf(a + n - 1)) { sc.v[a] = (uint8_t)((KIND_REP << 4) | lev); return; }
+                visit(sc, inf, lev - 1, a);
+                visit(sc, inf, lev - 1, a + n / 2);
+                return;
+            }
+            sc.v[a] = 0;
+        }
+    };
+    Rec::visit(sc, is_info, m, 0);
+    (void)n;
+    return sc;
+}
+
 template <int M, int L, bool FL>
 void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, uint32_t poly, uint8_t* anchors,
                  uint8_t* crc_ok, int32_t* pm, hipStream_t s)
@@ -309,7 +383,7 @@ void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, 
     constexpr int64_t per = WAVE / L;
     const int64_t blocks = (F + per - 1) / per;
     hipLaunchKernelGGL((scl_kernel<M, L, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, info[0], info[1],
-                       info[2], info[3], crc_len, poly, anchors, crc_ok, pm);
+                       info[2], info[3], crc_len, poly, make_sched(M, info), anchors, crc_ok, pm);
 }
 
 template <int M, bool FL>
