@@ -59,6 +59,11 @@ def cpu_baseline(wl, y, L, T, nframes, threads):
                       % (nframes, dt)}
 
 
+def _lib_variants():
+    from paper_2602_08501_amd import _lib
+    return _lib.mpwsd_search_variants()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -82,36 +87,56 @@ def main():
     st = D.Stage2([(code, F)], L, T, "i8", dev, want_moves=False)
     stream = torch.cuda.Stream()
     scale = float(wl.llr_scale)
-    from paper_2602_08501_amd import _lib
+    from paper_2602_08501_amd import autotune
 
-    def step(events=None):
-        _lib.check(_lib.mpwsd_quantize_llr(y_d.data_ptr(), y_d.numel(), scale, q_d.data_ptr(), None,
-                                           stream.cuda_stream))
+    def step_eager(events=None, variant=-1, bpc=0):
+        D.quantize(y_d, scale, out=q_d, stream=stream)
         D.stage1(code, L, q_d, wl.crc_len, wl.crc_poly, out=s1, stream=stream)
-        st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream, events=events)
+        st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream, events=events, variant=variant,
+               blocks_per_cu=bpc)
 
     with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-    torch.cuda.synchronize()
+        step_eager()
+        torch.cuda.synchronize()
+        variant, bpc = autotune.tune(st, [q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream)
 
-    # per-step search-kernel events (created by a first record on the stream)
-    evs = []
-    for _ in range(args.steps):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T)]
-        for x in e:
-            x.record(stream)
-        evs.append(e)
-    torch.cuda.synchronize()
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t_start.record(stream)
-    for k in range(args.steps):
-        step(evs[k])
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t_start.elapsed_time(t_end) / args.steps
+        # the whole step recorded once as a HIP graph, replayed per step
+        def record(raw):
+            D.quantize(y_d, scale, out=q_d, raw_stream=raw)
+            D.stage1(code, L, q_d, wl.crc_len, wl.crc_poly, out=s1, raw_stream=raw)
+            st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], variant=variant, blocks_per_cu=bpc, raw_stream=raw)
+
+        graph = D.Graph(record)
+        for _ in range(args.warmup):
+            graph.launch(stream)
+        torch.cuda.synchronize()
+
+        t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        t_start.record(stream)
+        for k in range(args.steps):
+            graph.launch(stream)
+        t_end.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = t_start.elapsed_time(t_end) / args.steps
+
+        # the same steps launched one by one with HIP events around every
+        # search kernel (its launch durations for the roofline entry)
+        evs = []
+        for _ in range(args.steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T)]
+            for x in e:
+                x.record(stream)
+            evs.append(e)
+        torch.cuda.synchronize()
+        e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e_start.record(stream)
+        for k in range(args.steps):
+            step_eager(evs[k], variant, bpc)
+        e_end.record(stream)
+        torch.cuda.synchronize()
+        ms_eager = e_start.elapsed_time(e_end) / args.steps
     stats = st.stats.cpu().numpy()
     cols = stats[1:1 + T].astype(np.int64)
     dense_ops = 2.0 * code.P * code.N * cols  # per launch
@@ -148,6 +173,9 @@ def main():
                      "launch_ms": launches.tolist(),
                      "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)"},
         "wall_s": wall,
+        "ms_per_step_eager": ms_eager,
+        "search_tiles": {"variant": variant, "blocks_per_cu": bpc,
+                         **_lib_variants()[variant]},
     }
     if args.cpu_frames > 0:
         thr = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -173,16 +173,56 @@ int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, int T,
                        hipStream_t stream);
 
 /*
- * mpwsd_decode_batch_timed - mpwsd_decode_batch that also records, on the
- * same stream, events[2 (s T + t)] right before and events[2 (s T + t) + 1]
- * right after the move-search kernel of iteration t of segment s, so the
- * caller can time the search with hipEventElapsedTime after its own sync.
- * events: host array of nseg * 2 * T events created by the caller.  Nothing
- * else differs; in particular nothing is synchronised.
+ * Tuning of the stage-2 move search.  The search kernel comes in a few tile
+ * shapes ("variants": column blocks of 16 per wave x waves per workgroup);
+ * all give bit-identical results, only their speed differs with the code
+ * and the number of active paths.
  */
-int mpwsd_decode_batch_timed(const mpwsd_segment* segs, int nseg, int L, int T,
-                             void* ws, size_t ws_bytes, int32_t* stats,
-                             hipEvent_t* events, hipStream_t stream);
+typedef struct mpwsd_variant_info {
+    int col_blocks;      /* 16-column MFMA blocks held per wave */
+    int waves;           /* waves per workgroup (they share each LDS move chunk) */
+    int columns;         /* paths per workgroup tile = 16 * col_blocks * waves */
+    int blocks_per_cu;   /* default workgroups per CU of the persistent grid */
+} mpwsd_variant_info;
+
+/* Number of search variants (>= 1); info[i] filled for i < min(n, cap). */
+int mpwsd_search_variants(mpwsd_variant_info* info, int cap);
+
+typedef struct mpwsd_options {
+    int search_variant;  /* 0 .. n-1, or -1 for the library default */
+    int blocks_per_cu;   /* persistent grid = CUs x this; 0 = the variant's default */
+    hipEvent_t* events;  /* NULL, or nseg * 2 * T events created by the caller:
+                            events[2 (s T + t)] is recorded right before and
+                            events[2 (s T + t) + 1] right after the search
+                            kernel of iteration t of segment s, on the same
+                            stream, for timing with hipEventElapsedTime */
+} mpwsd_options;
+
+/*
+ * mpwsd_decode_batch_ex - mpwsd_decode_batch with options (NULL = defaults).
+ * Nothing is synchronised in either form.
+ */
+int mpwsd_decode_batch_ex(const mpwsd_segment* segs, int nseg, int L, int T,
+                          void* ws, size_t ws_bytes, int32_t* stats,
+                          const mpwsd_options* options, hipStream_t stream);
+
+/*
+ * Recorded pipelines (HIP graphs).  Every call of this library is safe to
+ * record: kernel launches only, with all counts kept in device memory, no
+ * host synchronisation and no memset nodes.
+ *
+ * mpwsd_graph_begin creates a private stream in capture mode and returns
+ * it; the caller enqueues any sequence of mpwsd calls on it (nothing runs).
+ * mpwsd_graph_end stops the recording, instantiates the graph and destroys
+ * the stream.  mpwsd_graph_launch replays the recorded calls on a stream with
+ * the same buffers and sizes.  The graph object owns host-side driver
+ * resources only; buffers stay owned by the caller and must outlive it.
+ */
+typedef struct mpwsd_graph mpwsd_graph;
+int mpwsd_graph_begin(hipStream_t* record_stream);
+int mpwsd_graph_end(hipStream_t record_stream, mpwsd_graph** graph);
+int mpwsd_graph_launch(const mpwsd_graph* graph, hipStream_t stream);
+int mpwsd_graph_destroy(mpwsd_graph* graph);
 
 #ifdef __cplusplus
 }

@@ -28,6 +28,16 @@ class Segment(ctypes.Structure):
                 ("out_metric", _p), ("out_moves", _p)]
 
 
+class VariantInfo(ctypes.Structure):
+    """struct mpwsd_variant_info."""
+    _fields_ = [("col_blocks", _i), ("waves", _i), ("columns", _i), ("blocks_per_cu", _i)]
+
+
+class Options(ctypes.Structure):
+    """struct mpwsd_options."""
+    _fields_ = [("search_variant", _i), ("blocks_per_cu", _i), ("events", ctypes.POINTER(_p))]
+
+
 class MpwsdError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("%s (code %d)" % (msg, code))
@@ -52,10 +62,16 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_workspace_bytes.argtypes = [ctypes.POINTER(Segment), _i, _i, _i]
         lib.mpwsd_workspace_bytes.restype = _sz
         lib.mpwsd_decode_batch.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p, _p]
-        lib.mpwsd_decode_batch_timed.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p,
-                                                 ctypes.POINTER(_p), _p]
+        lib.mpwsd_decode_batch_ex.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p,
+                                              ctypes.POINTER(Options), _p]
+        lib.mpwsd_search_variants.argtypes = [ctypes.POINTER(VariantInfo), _i]
+        lib.mpwsd_graph_begin.argtypes = [ctypes.POINTER(_p)]
+        lib.mpwsd_graph_end.argtypes = [_p, ctypes.POINTER(_p)]
+        lib.mpwsd_graph_launch.argtypes = [_p, _p]
+        lib.mpwsd_graph_destroy.argtypes = [_p]
         for name in ("mpwsd_build_moves", "mpwsd_quantize_llr", "mpwsd_stage1_scl", "mpwsd_decode_batch",
-                     "mpwsd_decode_batch_timed"):
+                     "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
+                     "mpwsd_graph_launch", "mpwsd_graph_destroy"):
             getattr(lib, name).restype = _i
         _lib = lib
     return _lib
@@ -111,8 +127,40 @@ def mpwsd_decode_batch(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, s
     return load().mpwsd_decode_batch(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, stream)
 
 
-def mpwsd_decode_batch_timed(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, event_handles,
-                             stream) -> int:
+
+def mpwsd_decode_batch_ex(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, variant: int = -1,
+                          blocks_per_cu: int = 0, event_handles=None, stream=None) -> int:
     arr = segments_array(segs)
-    evs = (_p * len(event_handles))(*event_handles)
-    return load().mpwsd_decode_batch_timed(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, evs, stream)
+    opt = Options(variant, blocks_per_cu, None)
+    if event_handles is not None:
+        evs = (_p * len(event_handles))(*event_handles)
+        opt.events = ctypes.cast(evs, ctypes.POINTER(_p))
+    return load().mpwsd_decode_batch_ex(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, ctypes.byref(opt), stream)
+
+
+def mpwsd_search_variants() -> list:
+    n = load().mpwsd_search_variants(None, 0)
+    buf = (VariantInfo * n)()
+    load().mpwsd_search_variants(buf, n)
+    return [dict(col_blocks=v.col_blocks, waves=v.waves, columns=v.columns, blocks_per_cu=v.blocks_per_cu)
+            for v in buf]
+
+
+def mpwsd_graph_begin() -> int:
+    s = _p()
+    check(load().mpwsd_graph_begin(ctypes.byref(s)))
+    return s.value
+
+
+def mpwsd_graph_end(record_stream) -> int:
+    g = _p()
+    check(load().mpwsd_graph_end(record_stream, ctypes.byref(g)))
+    return g.value
+
+
+def mpwsd_graph_launch(graph, stream) -> int:
+    return load().mpwsd_graph_launch(graph, stream)
+
+
+def mpwsd_graph_destroy(graph) -> int:
+    return load().mpwsd_graph_destroy(graph)

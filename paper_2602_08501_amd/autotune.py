@@ -1,0 +1,98 @@
+"""Autotuner for the stage-2 move search.
+
+Times every search tile variant (column blocks per wave x waves per
+workgroup) and persistent-grid size on the caller's own batch, checks that
+all of them produce bit-identical decisions and move logs, and keeps the
+fastest.  Choices are cached per device, code, list size, iteration count and
+batch size in a JSON file (MPWSD_TUNE_CACHE, default
+~/.cache/mpwsd/tune.json).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import _lib
+
+CACHE = os.environ.get("MPWSD_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "mpwsd", "tune.json"))
+
+
+def _key(stage2, code, F) -> str:
+    name = torch.cuda.get_device_name(torch.device(stage2.device))
+    return "%s|RM(%d,%d)|L%d|T%d|F%d|%s" % (name, code.r, code.m, stage2.L, stage2.T, F,
+                                           "i8" if stage2.dt == _lib.MPWSD_I8 else "f32")
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(d: dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def candidates(N: int):
+    vs = _lib.mpwsd_search_variants()
+    kp = max(N, 64)
+    lds_fit = (160 * 1024) // (2 * 128 * (kp + 16))
+    out = []
+    for i, v in enumerate(vs):
+        for bpc in sorted({v["blocks_per_cu"], 1, 2, 3, 4}):
+            if 1 <= bpc <= lds_fit:
+                out.append((i, bpc))
+    return out
+
+
+def tune(stage2, llrs, anchors, crc_oks, reps: int = 3, stream=None, use_cache: bool = True, verbose=False):
+    """Returns (variant, blocks_per_cu) for this Stage2 and its inputs."""
+    code, F = stage2.codes_F[0]
+    key = _key(stage2, code, F)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        return tuple(cache[key]["choice"])
+    stream = stream or torch.cuda.current_stream()
+    T = stage2.T
+    nseg = len(stage2.codes_F)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T * nseg)]
+    for e in events:
+        e.record(stream)
+    ref = None
+    results = []
+    for var, bpc in candidates(code.N):
+        times = []
+        for r in range(reps + 1):
+            stage2.run(llrs, anchors, crc_oks, stream=stream, events=events, variant=var, blocks_per_cu=bpc)
+            stream.synchronize()
+            if r == 0:
+                out = {k: v.clone() for k, v in stage2.outs[0].items()}
+                if ref is None:
+                    ref = out
+                else:
+                    for k in ref:
+                        if not torch.equal(ref[k], out[k]):
+                            raise RuntimeError("search variant %d / %d differs from variant %d in %s"
+                                               % (var, bpc, results[0][1], k))
+                continue
+            times.append(sum(events[2 * t].elapsed_time(events[2 * t + 1]) for t in range(T * nseg)))
+        results.append((min(times), var, bpc))
+        if verbose:
+            print("variant %d blocks/CU %d: %.3f ms" % (var, bpc, min(times)))
+    best = min(results)
+    cache[key] = {"choice": [best[1], best[2]], "search_ms": best[0],
+                  "all": [[v, b, t] for t, v, b in results]}
+    if use_cache:
+        _save(cache)
+    return best[1], best[2]

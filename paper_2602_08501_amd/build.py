@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpwsd.so")
-SOURCES = ["moves.cpp", "stage1.hip", "stage2.hip"]
+SOURCES = ["moves.cpp", "graph.cpp", "stage1.hip", "stage2.hip"]
 ARCH = os.environ.get("MPWSD_ARCH", "gfx950")
 
 
@@ -23,7 +23,7 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-result",
+           "-Wall", "-Wno-unused-result", "-Wno-pass-failed",
            "-I", os.path.join(ROOT, "include"), "-o", tmp]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:

@@ -259,8 +259,8 @@ __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
     }
 }
 
-template <int N, int NC, int NWAVES>
-__global__ __launch_bounds__(NWAVES * WAVE, 2) void search_i8_kernel(
+template <int N, int NC, int NWAVES, int BPC>
+__global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
     const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
     const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, long long* __restrict__ keys)
 {
@@ -636,12 +636,34 @@ __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __res
 }
 
 // ---------------------------------------------------------------- launches
-template <int N>
-void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
+// Tile shapes of the int8 search (column blocks per wave, waves per
+// workgroup, default workgroups per CU).
+struct Variant {
+    int nc, nw, bpc;
+};
+constexpr Variant kVariants[] = {{8, 4, 2}, {4, 4, 4}, {4, 8, 2}, {8, 2, 4}, {2, 4, 4}};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+int default_variant(int N) { return N >= 256 ? 1 : 0; }
+
+template <int N, int V>
+void launch_search_i8_v(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
 {
-    constexpr int NC = 8, NW = 4;
-    hipLaunchKernelGGL((search_i8_kernel<N, NC, NW>), dim3(grid), dim3(NW * WAVE), 0, s, (const int8_t*)w.z,
-                       sg.moves, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
+    constexpr Variant v = kVariants[V];
+    hipLaunchKernelGGL((search_i8_kernel<N, v.nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s,
+                       (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
+}
+
+template <int N>
+void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int variant, int grid)
+{
+    switch (variant) {
+    case 0: launch_search_i8_v<N, 0>(w, sg, t, s, grid); break;
+    case 1: launch_search_i8_v<N, 1>(w, sg, t, s, grid); break;
+    case 2: launch_search_i8_v<N, 2>(w, sg, t, s, grid); break;
+    case 3: launch_search_i8_v<N, 3>(w, sg, t, s, grid); break;
+    default: launch_search_i8_v<N, 4>(w, sg, t, s, grid); break;
+    }
 }
 
 void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
@@ -658,7 +680,7 @@ void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream
 }
 
 int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipEvent_t* ev,
-                hipStream_t s)
+                int variant, int blocks_per_cu, hipStream_t s)
 {
     const int N = 1 << sg.m, KP = kpad(N);
     const bool fl = sg.dtype == MPWSD_F32;
@@ -688,11 +710,16 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
                                N, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
                                (unsigned long long*)w.key64, w.fid, L, sg.out_moves);
         } else {
+            const int var = variant >= 0 ? variant : default_variant(N);
+            // workgroups per CU: requested, else the variant's default capped
+            // by how many fit in the 160 KB LDS of a CU
+            const int lds_fit = (160 * 1024) / (2 * RC * (KP + 16));
+            const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
             switch (N) {
-            case 32: launch_search_i8<32>(w, sg, t, s, cus * 2); break;
-            case 64: launch_search_i8<64>(w, sg, t, s, cus * 2); break;
-            case 128: launch_search_i8<128>(w, sg, t, s, cus * 2); break;
-            default: launch_search_i8<256>(w, sg, t, s, cus * 2); break;
+            case 32: launch_search_i8<32>(w, sg, t, s, var, grid); break;
+            case 64: launch_search_i8<64>(w, sg, t, s, var, grid); break;
+            case 128: launch_search_i8<128>(w, sg, t, s, var, grid); break;
+            default: launch_search_i8<256>(w, sg, t, s, var, grid); break;
             }
             if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
             hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
@@ -753,10 +780,15 @@ extern "C" size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int
 
 namespace {
 int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t ws_bytes, int32_t* stats,
-           hipEvent_t* events, hipStream_t stream)
+           const mpwsd_options* opt, hipStream_t stream)
 {
     int rc = validate(segs, nseg, L, T, true);
     if (rc != MPWSD_OK) return rc;
+    const int variant = opt ? opt->search_variant : -1;
+    const int bpc = opt ? opt->blocks_per_cu : 0;
+    if (variant < -1 || variant >= kNumVariants)
+        return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: search_variant %d out of range", variant);
+    if (bpc < 0 || bpc > 16) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: blocks_per_cu %d", bpc);
     size_t need = 0;
     for (int i = 0; i < nseg; ++i) need += carve(segs[i], L, T, nullptr).bytes;
     if (!ws || ws_bytes < need)
@@ -769,7 +801,8 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
         SegWs w = carve(segs[i], L, T, base);
         base += w.bytes;
         if (segs[i].F == 0) continue;
-        rc = run_segment(segs[i], L, T, w, stats, events ? events + (size_t)2 * T * i : nullptr, stream);
+        hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
+        rc = run_segment(segs[i], L, T, w, stats, ev, variant, bpc, stream);
         if (rc != MPWSD_OK) return rc;
     }
     return MPWSD_OK;
@@ -783,10 +816,17 @@ extern "C" int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, in
     return decode(segs, nseg, L, T, ws, ws_bytes, stats, nullptr, stream);
 }
 
-extern "C" int mpwsd_decode_batch_timed(const mpwsd_segment* segs, int nseg, int L, int T, void* ws,
-                                        size_t ws_bytes, int32_t* stats, hipEvent_t* events, hipStream_t stream)
+extern "C" int mpwsd_decode_batch_ex(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t ws_bytes,
+                                     int32_t* stats, const mpwsd_options* options, hipStream_t stream)
 {
     mpwsd::clear_error();
-    if (!events) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch_timed: events is NULL");
-    return decode(segs, nseg, L, T, ws, ws_bytes, stats, events, stream);
+    return decode(segs, nseg, L, T, ws, ws_bytes, stats, options, stream);
+}
+
+extern "C" int mpwsd_search_variants(mpwsd_variant_info* info, int cap)
+{
+    for (int i = 0; i < kNumVariants && info && i < cap; ++i)
+        info[i] = mpwsd_variant_info{kVariants[i].nc, kVariants[i].nw, 16 * kVariants[i].nc * kVariants[i].nw,
+                                     kVariants[i].bpc};
+    return kNumVariants;
 }

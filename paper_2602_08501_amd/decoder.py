@@ -42,15 +42,37 @@ class Code:
         self.K = sum(math.comb(m, d) for d in range(r + 1))
 
 
-def quantize(y: torch.Tensor, scale: float, bad: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    q = torch.empty(y.shape, dtype=torch.int8, device=y.device)
+def quantize(y: torch.Tensor, scale: float, bad: torch.Tensor | None = None, stream=None,
+             out: torch.Tensor | None = None, raw_stream=None) -> torch.Tensor:
+    q = out if out is not None else torch.empty(y.shape, dtype=torch.int8, device=y.device)
     check(_lib.mpwsd_quantize_llr(y.data_ptr(), y.numel(), float(np.float32(scale)), q.data_ptr(),
-                                  _ptr(bad), _stream(stream)))
+                                  _ptr(bad), raw_stream if raw_stream is not None else _stream(stream)))
     return q
 
 
+class Graph:
+    """A recorded sequence of library calls (HIP graph), replayed with launch()."""
+
+    def __init__(self, record):
+        """record(raw_stream) enqueues the calls to record on raw_stream."""
+        s = _lib.mpwsd_graph_begin()
+        try:
+            record(s)
+        finally:
+            self.handle = _lib.mpwsd_graph_end(s)
+
+    def launch(self, stream=None):
+        check(_lib.mpwsd_graph_launch(self.handle, _stream(stream)))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.mpwsd_graph_destroy(h)
+            self.handle = None
+
+
 def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: int = 0x43,
-           out=None, stream=None, want_pm: bool = False):
+           out=None, stream=None, want_pm: bool = False, raw_stream=None):
     F = llr.shape[0]
     dev = llr.device
     if out is None:
@@ -61,7 +83,7 @@ def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: in
     dtype = MPWSD_I8 if llr.dtype == torch.int8 else MPWSD_F32
     check(_lib.mpwsd_stage1_scl(code.r, code.m, crc_len, crc_poly, L, llr.data_ptr(), dtype, F,
                                 out["anchors"].data_ptr(), out["crc_ok"].data_ptr(),
-                                _ptr(out.get("pm")), _stream(stream)))
+                                _ptr(out.get("pm")), raw_stream if raw_stream is not None else _stream(stream)))
     return out
 
 
@@ -100,15 +122,19 @@ class Stage2:
                                 _ptr(o.get("moves")) if o else None))
         return segs
 
-    def run(self, llrs, anchors, crc_oks, stream=None, events=None):
+    def run(self, llrs, anchors, crc_oks, stream=None, events=None, variant: int = -1, blocks_per_cu: int = 0,
+            raw_stream=None):
         """events: optional list of 2 * T * nseg recorded torch.cuda.Event
-        (enable_timing=True); re-recorded around every search launch."""
+        (enable_timing=True); re-recorded around every search launch.
+        raw_stream: a hipStream_t handle (int) to enqueue on instead of a
+        torch stream (used while recording a graph)."""
         segs = self._segs(llrs, anchors, crc_oks)
-        if events is None:
+        st = raw_stream if raw_stream is not None else _stream(stream)
+        if events is None and variant < 0 and blocks_per_cu == 0:
             check(_lib.mpwsd_decode_batch(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
-                                          self.stats.data_ptr(), _stream(stream)))
+                                          self.stats.data_ptr(), st))
         else:
-            check(_lib.mpwsd_decode_batch_timed(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
-                                                self.stats.data_ptr(), [e.cuda_event for e in events],
-                                                _stream(stream)))
+            check(_lib.mpwsd_decode_batch_ex(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
+                                             self.stats.data_ptr(), variant, blocks_per_cu,
+                                             None if events is None else [e.cuda_event for e in events], st))
         return self.outs

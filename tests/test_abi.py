@@ -16,7 +16,8 @@ def test_library_exports_every_declared_call():
     names = _lib.header_functions()
     assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_quantize_llr",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
-                          "mpwsd_decode_batch_timed"}
+                          "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
+                          "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy"}
     for n in names:
         assert hasattr(lib, n), n
 
@@ -113,3 +114,16 @@ def test_stage1_validates_before_enqueue():
     assert _lib.mpwsd_quantize_llr(None, 0, 1.0, None, None, None) == 0
     assert _lib.mpwsd_quantize_llr(None, 5, 1.0, None, None, None) == _lib.MPWSD_ERR_ARG
     assert _lib.mpwsd_quantize_llr(A, 5, float("inf"), A, None, None) == _lib.MPWSD_ERR_ARG
+
+
+def test_search_variants_and_option_errors():
+    vs = _lib.mpwsd_search_variants()
+    assert len(vs) >= 2
+    for v in vs:
+        assert v["columns"] == 16 * v["col_blocks"] * v["waves"]
+    ok = _lib.mpwsd_workspace_bytes([_seg()], 8, 8)
+    assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, variant=len(vs)) == _lib.MPWSD_ERR_ARG
+    assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, variant=-2) == _lib.MPWSD_ERR_ARG
+    assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, blocks_per_cu=-1) == _lib.MPWSD_ERR_ARG
+    assert _lib.load().mpwsd_graph_launch(None, None) == _lib.MPWSD_ERR_ARG
+    assert _lib.load().mpwsd_graph_destroy(None) == 0
