@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-frames", type=int, default=8192, help="oracle sample size (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a reference dispatch of "
+                         "known traffic for hardware counters)")
     return ap.parse_args()
 
 
@@ -57,6 +60,22 @@ def cpu_baseline(wl, y, L, T, nframes, threads):
     return {"value": nframes / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
             "sample": "first %d frames of the same batch (int8 LLRs, full two-stage decode), %.1f s wall"
                       % (nframes, dt)}
+
+
+def recorded_traffic():
+    """HBM bytes per search launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "search_i8_rm37_65536f_hbm_traffic.txt")
+    try:
+        m = re.search(r"bench-traffic: source=(\S+) sha256=(\w+) hbm_bytes_per_launch=(\d+)", open(path).read())
+        src = open(os.path.join(ROOT, m.group(1)), "rb").read()
+    except (OSError, AttributeError):
+        return None
+    if hashlib.sha256(src).hexdigest() != m.group(2):
+        return None
+    return int(m.group(3))
 
 
 def _lib_variants():
@@ -88,6 +107,12 @@ def main():
     stream = torch.cuda.Stream()
     scale = float(wl.llr_scale)
     from paper_2602_08501_amd import autotune
+    if args.calib_copy > 0:
+        src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step_eager(events=None, variant=-1, bpc=0):
         D.quantize(y_d, scale, out=q_d, stream=stream)
@@ -168,7 +193,8 @@ def main():
                    "paths_searched_per_iteration": cols.tolist(), "fer": fer},
         "stage2_move_evals_per_s": moves_evals / (launches.sum() * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_INT8_DENSE_TOPS, "unit": "TOP/s",
-                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": None,
+                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 KiB)",
                      "kernel": "search_i8_kernel",
                      "launch_ms": launches.tolist(),
                      "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)"},
