@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--L", type=int, default=8)
     ap.add_argument("--T", type=int, default=8)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-frames", type=int, default=8192, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=16384, help="oracle sample size (0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a reference dispatch of "

@@ -1,0 +1,100 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (whole step recorded as a HIP graph, autotuned search tiles), checked
+against the oracle on sampled frames (every frame is decoded independently,
+so the oracle decodes the sampled rows alone)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_08501_amd import autotune
+from paper_2602_08501_amd import decoder as D
+from paper_2602_08501_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_pipeline(wl, F, L, T, seed):
+    pay, c, y = synth.generate(wl, seed, 0, F)
+    code = D.Code(wl.r, wl.m, DEV)
+    y_d = torch.from_numpy(y).to(DEV)
+    q = torch.empty(y.shape, dtype=torch.int8, device=DEV)
+    s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=DEV),
+          "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)}
+    st = D.Stage2([(code, F)], L, T, "i8", DEV)
+    scale = float(wl.llr_scale)
+    D.quantize(y_d, scale, out=q)
+    D.stage1(code, L, q, wl.crc_len, wl.crc_poly, out=s1)
+    torch.cuda.synchronize()
+    variant, bpc = autotune.tune(st, [q], [s1["anchors"]], [s1["crc_ok"]], reps=1, use_cache=False)
+
+    def record(raw):
+        D.quantize(y_d, scale, out=q, raw_stream=raw)
+        D.stage1(code, L, q, wl.crc_len, wl.crc_poly, out=s1, raw_stream=raw)
+        st.run([q], [s1["anchors"]], [s1["crc_ok"]], variant=variant, blocks_per_cu=bpc, raw_stream=raw)
+
+    g = D.Graph(record)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in st.outs[0].items()}
+    out["crc_ok"] = s1["crc_ok"].cpu().numpy()
+    out["anchors"] = s1["anchors"].cpu().numpy()
+    out["q"] = q.cpu().numpy()
+    stats = st.stats.cpu().numpy()
+    del g
+    return c, y, out, stats, (variant, bpc)
+
+
+def check_sample(wl, L, T, out, rows):
+    q = out["q"][rows].astype(np.float64)
+    ref = oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=8)
+    cw = np.unpackbits(out["cw"][rows], axis=-1, bitorder="little")
+    anc = np.unpackbits(out["anchors"][rows], axis=-1, bitorder="little")
+    assert np.array_equal(out["crc_ok"][rows], ref["crc_ok"])
+    assert np.array_equal(anc, ref["anchors"])
+    assert np.array_equal(out["moves"][rows], ref["logs"])
+    assert np.array_equal(cw, ref["c"])
+    assert np.array_equal(out["k"][rows], ref["k"])
+    assert np.array_equal(out["metric"][rows], ref["metric"].astype(np.int32))
+
+
+def test_rm37_bench_size():
+    wl = synth.RM37
+    F, L, T = 65536, 8, 8
+    say("case: RM(3,7) 65536 frames, graph + autotuned tiles")
+    c, y, out, stats, tiles = run_pipeline(wl, F, L, T, 0)
+    say("  tiles", tiles, "stats", stats.tolist())
+    fail = np.nonzero(out["crc_ok"] == 0)[0]
+    assert stats[0] == len(fail) and stats[1] == len(fail) * L and stats[-1] == 0
+    # every logged move count matches the next iteration's searched paths
+    logs = out["moves"][fail]
+    for t in range(1, T):
+        assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
+    rng = np.random.default_rng(0)
+    rows = np.sort(np.concatenate([rng.choice(fail, 160, replace=False),
+                                   rng.choice(np.nonzero(out["crc_ok"])[0], 64, replace=False),
+                                   [0, F - 1]]))
+    check_sample(wl, L, T, out, rows)
+
+
+def test_rm38_config_size():
+    wl = synth.RM38
+    F, L, T = 32768, 16, 12
+    say("case: RM(3,8) 32768 frames, graph + autotuned tiles")
+    c, y, out, stats, tiles = run_pipeline(wl, F, L, T, 0)
+    say("  tiles", tiles, "stats", stats.tolist())
+    fail = np.nonzero(out["crc_ok"] == 0)[0]
+    assert stats[0] == len(fail) and stats[-1] == 0
+    rng = np.random.default_rng(1)
+    rows = np.sort(np.concatenate([rng.choice(fail, 6, replace=False),
+                                   rng.choice(np.nonzero(out["crc_ok"])[0], 10, replace=False)]))
+    check_sample(wl, L, T, out, rows)
