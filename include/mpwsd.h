@@ -224,6 +224,87 @@ int mpwsd_graph_end(hipStream_t record_stream, mpwsd_graph** graph);
 int mpwsd_graph_launch(const mpwsd_graph* graph, hipStream_t stream);
 int mpwsd_graph_destroy(mpwsd_graph* graph);
 
+/*
+ * Serving: continuous batching of arriving frames (int8 LLRs).
+ *
+ * A server holds, per code, a pool of frame slots in a device arena the
+ * caller provides (the memory gate: at most `capacity` frames of that code
+ * are in flight).  Each tick
+ *   1. admits waiting frames into free slots, uploads their received values,
+ *      quantizes them with their own scale and runs stage 1 on them; frames
+ *      whose best list entry passes the CRC complete in this tick;
+ *   2. appends the L paths of the other new frames to the code's pool of
+ *      active paths, which holds the paths of frames admitted in earlier
+ *      ticks as well;
+ *   3. runs ONE stage-2 iteration (search + apply) over the whole pool: new
+ *      and old paths share the same launches;
+ *   4. completes every frame whose L paths have all stopped (no improving
+ *      move, or T accepted moves), with the same choice rule as
+ *      mpwsd_decode_batch, and frees its slot once the host has read it.
+ * A frame's result therefore does not depend on which other frames share
+ * its ticks: it equals mpwsd_decode_batch's result for that frame alone.
+ * Ticks run asynchronously on the server's stream; up to two are in flight.
+ */
+typedef struct mpwsd_server mpwsd_server;
+
+typedef struct mpwsd_server_code {
+    int r, m;                /* RM(r, m), 5 <= m <= 8 */
+    const uint8_t* moves;    /* device [P][N/8] move table (mpwsd_build_moves) */
+    int64_t P;
+    int L, T;                /* list size (power of two <= 32), iterations */
+    int crc_len;             /* CRC length (0: no CRC, every frame goes on) */
+    uint32_t crc_poly;
+    int capacity;            /* frames of this code in flight at most */
+} mpwsd_server_code;
+
+typedef struct mpwsd_result {
+    uint64_t tag;            /* the caller's tag of the frame */
+    int32_t code;            /* index of the code in the server */
+    int32_t stage;           /* 1: decided by stage 1, 2: by stage 2 */
+    int32_t k;               /* chosen path (0 for stage 1) */
+    int32_t metric;          /* M(c) = sum_{c_j=1} q_j of the decision */
+    uint8_t cw[32];          /* decision, N/8 bytes used */
+    double t_submit;         /* host seconds (steady clock) at submission */
+    double t_done;           /* host seconds at which the host saw the result */
+} mpwsd_result;
+
+/* Device arena bytes needed by mpwsd_server_create for these codes. */
+size_t mpwsd_server_arena_bytes(const mpwsd_server_code* codes, int ncodes);
+
+/* Creates a server; arena (device, 256-byte aligned) stays owned by the
+ * caller and must outlive the server.  The server allocates pinned host
+ * staging buffers, one stream and events (host-side driver resources). */
+int mpwsd_server_create(const mpwsd_server_code* codes, int ncodes, void* arena, size_t arena_bytes,
+                        mpwsd_server** server);
+
+/* Queues n frames of code `code`: y host [n][N] float, scale[n] quantizer
+ * scales (8 / sigma^2), tags[n].  The data is copied; nothing is enqueued. */
+int mpwsd_server_submit(mpwsd_server* server, int code, int n, const float* y, const float* scale,
+                        const uint64_t* tags);
+
+/* Harvests finished ticks, admits waiting frames and enqueues one tick when
+ * there is work.  *in_flight (may be NULL) receives the number of frames
+ * submitted but not yet returned by mpwsd_server_poll. */
+int mpwsd_server_tick(mpwsd_server* server, int64_t* in_flight);
+
+/* Moves up to cap completed results to out; returns how many (>= 0). */
+int mpwsd_server_poll(mpwsd_server* server, mpwsd_result* out, int cap);
+
+/* Synchronises the server's stream and releases everything it owns. */
+int mpwsd_server_destroy(mpwsd_server* server);
+
+/*
+ * mpwsd_serve_trace - a real-time load generator around a server: frame i of
+ * the trace (code[i], y row row[i] of that code's pool, scale[i]) is
+ * submitted when arrival[i] seconds have passed since the start, the server
+ * is ticked continuously, and the result of frame i is written to out[i]
+ * (tag = i).  pools[c] is a host [rows][N] float array for code c.
+ * Returns 0 when every frame completed.
+ */
+int mpwsd_serve_trace(mpwsd_server* server, int64_t n, const int32_t* code, const int64_t* row,
+                      const float* scale, const double* arrival, const float* const* pools,
+                      mpwsd_result* out);
+
 #ifdef __cplusplus
 }
 #endif

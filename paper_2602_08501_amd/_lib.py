@@ -38,6 +38,19 @@ class Options(ctypes.Structure):
     _fields_ = [("search_variant", _i), ("blocks_per_cu", _i), ("events", ctypes.POINTER(_p))]
 
 
+class ServerCode(ctypes.Structure):
+    """struct mpwsd_server_code."""
+    _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("L", _i), ("T", _i), ("crc_len", _i),
+                ("crc_poly", _u32), ("capacity", _i)]
+
+
+class Result(ctypes.Structure):
+    """struct mpwsd_result."""
+    _fields_ = [("tag", ctypes.c_uint64), ("code", ctypes.c_int32), ("stage", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("metric", ctypes.c_int32), ("cw", ctypes.c_uint8 * 32),
+                ("t_submit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 class MpwsdError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("%s (code %d)" % (msg, code))
@@ -69,9 +82,18 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_graph_end.argtypes = [_p, ctypes.POINTER(_p)]
         lib.mpwsd_graph_launch.argtypes = [_p, _p]
         lib.mpwsd_graph_destroy.argtypes = [_p]
+        lib.mpwsd_server_arena_bytes.argtypes = [ctypes.POINTER(ServerCode), _i]
+        lib.mpwsd_server_arena_bytes.restype = _sz
+        lib.mpwsd_server_create.argtypes = [ctypes.POINTER(ServerCode), _i, _p, _sz, ctypes.POINTER(_p)]
+        lib.mpwsd_server_submit.argtypes = [_p, _i, _i, _p, _p, _p]
+        lib.mpwsd_server_tick.argtypes = [_p, ctypes.POINTER(ctypes.c_int64)]
+        lib.mpwsd_server_poll.argtypes = [_p, ctypes.POINTER(Result), _i]
+        lib.mpwsd_server_destroy.argtypes = [_p]
+        lib.mpwsd_serve_trace.argtypes = [_p, _i64, _p, _p, _p, _p, ctypes.POINTER(_p), ctypes.POINTER(Result)]
         for name in ("mpwsd_build_moves", "mpwsd_quantize_llr", "mpwsd_stage1_scl", "mpwsd_decode_batch",
                      "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
-                     "mpwsd_graph_launch", "mpwsd_graph_destroy"):
+                     "mpwsd_graph_launch", "mpwsd_graph_destroy", "mpwsd_server_create", "mpwsd_server_submit",
+                     "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"):
             getattr(lib, name).restype = _i
         _lib = lib
     return _lib

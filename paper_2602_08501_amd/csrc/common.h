@@ -4,6 +4,8 @@
 #include <cstdarg>
 #include <cstdint>
 
+#include <hip/hip_runtime_api.h>
+
 #include "mpwsd.h"
 
 namespace mpwsd {
@@ -17,5 +19,15 @@ int rm_dimension(int r, int m);
 
 // Number of minimum-weight codewords of RM(r, m) (flats of dimension m - r).
 int64_t rm_min_weight_count(int r, int m);
+
+// Compute units of the current device (cached per device).
+int device_cu_count();
+
+// Enqueue the int8 move search (stage 2) over the active columns act[0 .. *count)
+// (count read on the device): per column the minimum (S << 32 | p) is folded
+// into keys[column] with atomicMin.  zneg holds -z per column, padded to
+// max(N, 64) bytes.  variant / blocks_per_cu as in mpwsd_options.
+void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
+                      const int32_t* count, long long* keys, int variant, int blocks_per_cu, hipStream_t s);
 
 }  // namespace mpwsd

@@ -1,0 +1,590 @@
+// Serving: continuous batching of arriving frames over persistent per-code
+// state in a caller-provided device arena (see mpwsd.h).
+//
+// Per code the arena holds a pool of `capacity` frame slots; a frame's L
+// paths are the columns slot * L + k.  Every tick enqueues, on the server's
+// stream:
+//   H2D of the newly admitted frames  -> quantize (per-frame scale)
+//   -> stage 1 (mpwsd_stage1_scl on the contiguous new frames)
+//   -> enter: decided frames emit a result record, the others' paths join
+//      the active list that already holds older paths
+//   -> one search over the whole active list -> resolve: apply moves; paths
+//      that stop (no improving move or T moves) count down their frame, and
+//      the last one to stop chooses the frame's decision and emits a record
+//   -> D2H of the result records.
+// Paths that move and have iterations left form the next tick's list.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+
+struct Record {
+    int32_t slot, stage, k, metric;
+    uint8_t cw[32];
+};
+
+enum { H_CNT0 = 0, H_CNT1 = 1, H_CCOUNT = 2, H_ERR = 3, H_WORDS = 64 };
+
+// Position of this lane's item in a list appended to by the whole wave (one
+// atomic per wave).  Every lane of the wave must call it.
+__device__ inline int wave_append(bool flag, int32_t* counter)
+{
+    const uint64_t bal = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(counter, __popcll(bal));
+    base = __shfl(base, 0);
+    return base + __popcll(bal & ((1ull << lane) - 1ull));
+}
+
+__global__ void srv_prep_kernel(int32_t* hdr, int nxt)
+{
+    if (threadIdx.x == 0) {
+        hdr[nxt ? H_CNT1 : H_CNT0] = 0;
+        hdr[H_CCOUNT] = 0;
+    }
+}
+
+__global__ void srv_quantize_kernel(const float* __restrict__ y, const float* __restrict__ scale, int n, int N,
+                                    int8_t* __restrict__ q, int32_t* __restrict__ hdr)
+{
+    const int64_t total = (int64_t)n * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = y[i];
+        if (!isfinite(v)) {
+            q[i] = 0;
+            atomicAdd(&hdr[H_ERR], 1);
+            continue;
+        }
+        float t = rintf(__fmul_rn(v, scale[i / N]));
+        t = fminf(fmaxf(t, -127.0f), 127.0f);
+        q[i] = (int8_t)t;
+    }
+}
+
+// thread per (new frame, path); a frame's L threads are consecutive lanes
+__global__ __launch_bounds__(256) void srv_enter_kernel(
+    int n, int L, int N, int KP, const int8_t* __restrict__ q, const uint8_t* __restrict__ anc,
+    const uint8_t* __restrict__ ok, const int32_t* __restrict__ newslot, uint8_t* __restrict__ cw,
+    int8_t* __restrict__ zneg, int32_t* __restrict__ metric, int32_t* __restrict__ citer, long long* __restrict__ key,
+    int32_t* __restrict__ fdone, int32_t* __restrict__ act, int32_t* __restrict__ hdr, int cur,
+    Record* __restrict__ rec)
+{
+    const int NB = N / 8;
+    const int total = n * L;
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < total; base += gridDim.x * blockDim.x) {
+        const int idx = base + (threadIdx.x & 63);
+        const bool live = idx < total;
+        const int i = live ? idx / L : 0, k = live ? idx % L : 0;
+        const bool decided = live && ok[i];
+        const uint8_t* a = anc + ((size_t)i * L + k) * NB;
+        const int8_t* qi = q + (size_t)i * N;
+        const int slot = live ? newslot[i] : 0;
+        int m = 0;
+        if (live && (!decided || k == 0))
+            for (int j = 0; j < N; ++j) m += ((a[j >> 3] >> (j & 7)) & 1) ? qi[j] : 0;
+        // a decided frame emits its result record
+        const bool emit = decided && k == 0;
+        const int rpos = wave_append(emit, &hdr[H_CCOUNT]);
+        if (emit) {
+            Record& r = rec[rpos];
+            r.slot = slot;
+            r.stage = 1;
+            r.k = 0;
+            r.metric = m;
+            for (int b = 0; b < NB; ++b) r.cw[b] = a[b];
+        }
+        // the paths of the other new frames become active columns
+        const bool join = live && !decided;
+        const int col = slot * L + k;
+        if (join) {
+            for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = a[b];
+            int8_t* z = zneg + (size_t)col * KP;
+            for (int j = 0; j < KP; ++j) {
+                const int bit = j < N ? (a[j >> 3] >> (j & 7)) & 1 : 0;
+                const int v = j < N ? qi[j] : 0;
+                z[j] = (int8_t)(bit ? v : -v);  // -z
+            }
+            metric[col] = m;
+            citer[col] = 0;
+            key[col] = LLONG_MAX;
+            if (k == 0) fdone[slot] = 0;
+        }
+        const int apos = wave_append(join, &hdr[cur ? H_CNT1 : H_CNT0]);
+        if (join) act[apos] = col;
+    }
+}
+
+// thread per active column
+__global__ __launch_bounds__(256) void srv_resolve_kernel(
+    int L, int T, int N, int KP, int64_t P, const uint8_t* __restrict__ moves, uint8_t* __restrict__ cw,
+    int8_t* __restrict__ zneg, int32_t* __restrict__ metric, int32_t* __restrict__ citer, long long* __restrict__ key,
+    int32_t* __restrict__ fdone, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
+    int32_t* __restrict__ hdr, int cur, Record* __restrict__ rec)
+{
+    const int NB = N / 8, NWD = N / 32;
+    const int n = hdr[cur ? H_CNT1 : H_CNT0];
+    int32_t* cnt_out = &hdr[cur ? H_CNT0 : H_CNT1];
+    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += gridDim.x * blockDim.x) {
+        const int pos = base + (threadIdx.x & 63);
+        bool cont = false, fin = false;
+        int col = 0;
+        if (pos < n) {
+            col = act_in[pos];
+            const long long kv = key[col];
+            key[col] = LLONG_MAX;
+            const int S = (int)(kv >> 32);
+            const int64_t p = (int64_t)(uint32_t)kv;
+            const bool moved = kv != LLONG_MAX && S < 0 && p < P;
+            if (moved) {
+                const uint32_t* mv = (const uint32_t*)(moves + (size_t)p * NB);
+                uint32_t* c32 = (uint32_t*)(cw + (size_t)col * NB);
+                int8_t* zc = zneg + (size_t)col * KP;
+                for (int wd = 0; wd < NWD; ++wd) {
+                    uint32_t bits = mv[wd];
+                    c32[wd] ^= bits;
+                    while (bits) {
+                        const int j = 32 * wd + __builtin_ctz(bits);
+                        zc[j] = (int8_t)(-zc[j]);
+                        bits &= bits - 1;
+                    }
+                }
+                metric[col] += S;
+                citer[col] += 1;
+            }
+            cont = moved && citer[col] < T;
+            fin = !cont;
+        }
+        const int apos = wave_append(cont, cnt_out);
+        if (cont) act_out[apos] = col;
+        bool emit = false;
+        int slot = 0, kb = 0, mb = 0;
+        if (fin) {
+            slot = col / L;
+            __threadfence();
+            if (atomicAdd(&fdone[slot], 1) == L - 1) {
+                __threadfence();
+                // every path of this frame has stopped: the choice of Alg. 1
+                mb = metric[(size_t)slot * L];
+                for (int k = 1; k < L; ++k) {
+                    const int v = metric[(size_t)slot * L + k];
+                    if (v < mb) { mb = v; kb = k; }
+                }
+                emit = true;
+            }
+        }
+        const int rpos = wave_append(emit, &hdr[H_CCOUNT]);
+        if (emit) {
+            Record& r = rec[rpos];
+            r.slot = slot;
+            r.stage = 2;
+            r.k = kb;
+            r.metric = mb;
+            const uint8_t* c = cw + ((size_t)slot * L + kb) * NB;
+            for (int b = 0; b < NB; ++b) r.cw[b] = c[b];
+        }
+    }
+}
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct CodeLayout {
+    size_t yst, sst, qst, ancst, okst, newslot, cw, zneg, metric, citer, key, fdone, act0, act1, hdr, rec, bytes;
+};
+
+CodeLayout layout(const mpwsd_server_code& c)
+{
+    const size_t C = (size_t)c.capacity, N = (size_t)1 << c.m, KP = N < 64 ? 64 : N, L = (size_t)c.L;
+    CodeLayout l{};
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t o = off; off += al(b); return o; };
+    l.yst = take(C * N * 4);
+    l.sst = take(C * 4);
+    l.qst = take(C * N);
+    l.ancst = take(C * L * N / 8);
+    l.okst = take(C);
+    l.newslot = take(C * 4);
+    l.cw = take(C * L * N / 8);
+    l.zneg = take(C * L * KP);
+    l.metric = take(C * L * 4);
+    l.citer = take(C * L * 4);
+    l.key = take(C * L * 8);
+    l.fdone = take(C * 4);
+    l.act0 = take(C * L * 4);
+    l.act1 = take(C * L * 4);
+    l.hdr = take(H_WORDS * 4);
+    l.rec = take(C * sizeof(Record));
+    l.bytes = off;
+    return l;
+}
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Pending {
+    uint64_t tag;
+    float scale;
+    double t_submit;
+    std::vector<float> y;
+};
+
+struct Code {
+    mpwsd_server_code c;
+    int N, KP, NB;
+    CodeLayout lay;
+    uint8_t* base;
+    std::vector<int> free_slots;
+    std::vector<uint64_t> slot_tag;
+    std::vector<double> slot_t;
+    std::deque<Pending> waiting;
+    int in_slots = 0;  // admitted, not yet harvested
+    int cur = 0;       // active list the next tick searches
+    template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+};
+
+struct TickBuf {
+    hipEvent_t ev = nullptr;
+    bool busy = false;
+    struct PerCode {
+        float* y = nullptr;       // pinned [capacity][N]
+        float* scale = nullptr;   // pinned [capacity]
+        int32_t* slot = nullptr;  // pinned [capacity]
+        int32_t* hdr = nullptr;   // pinned [H_WORDS]
+        Record* rec = nullptr;    // pinned [capacity]
+        int maxrec = 0;
+    };
+    std::vector<PerCode> pc;
+};
+
+}  // namespace
+
+struct mpwsd_server {
+    std::vector<Code> codes;
+    hipStream_t stream = nullptr;
+    TickBuf ticks[2];
+    int next_tick = 0;
+    std::deque<mpwsd_result> done;
+    int64_t submitted = 0, returned = 0;
+};
+
+namespace {
+
+int check_codes(const mpwsd_server_code* codes, int ncodes)
+{
+    using mpwsd::fail;
+    if (!codes || ncodes < 1 || ncodes > 16) return fail(MPWSD_ERR_ARG, "server: need 1..16 codes");
+    for (int i = 0; i < ncodes; ++i) {
+        const auto& c = codes[i];
+        if (c.m < 5 || c.m > 8 || c.r < 1 || c.r >= c.m)
+            return fail(MPWSD_ERR_UNSUPPORTED, "server code %d: need 1 <= r < m, 5 <= m <= 8", i);
+        if (c.P != mpwsd::rm_min_weight_count(c.r, c.m))
+            return fail(MPWSD_ERR_ARG, "server code %d: P is not the move count of RM(%d,%d)", i, c.r, c.m);
+        if (c.L < 1 || c.L > 32 || (c.L & (c.L - 1)) || c.T < 1 || c.T > 64)
+            return fail(MPWSD_ERR_UNSUPPORTED, "server code %d: L must be a power of two <= 32, 1 <= T <= 64", i);
+        if (c.capacity < 1 || (int64_t)c.capacity * c.L > (1 << 26))
+            return fail(MPWSD_ERR_ARG, "server code %d: bad capacity %d", i, c.capacity);
+        if (!c.moves) return fail(MPWSD_ERR_ARG, "server code %d: moves is NULL", i);
+    }
+    return MPWSD_OK;
+}
+
+void harvest(mpwsd_server* s, TickBuf& tb)
+{
+    const double t = now_s();
+    for (size_t ci = 0; ci < s->codes.size(); ++ci) {
+        Code& c = s->codes[ci];
+        TickBuf::PerCode& p = tb.pc[ci];
+        const int nrec = std::min(p.hdr[H_CCOUNT], p.maxrec);
+        for (int i = 0; i < nrec; ++i) {
+            const Record& r = p.rec[i];
+            mpwsd_result res{};
+            res.tag = c.slot_tag[r.slot];
+            res.code = (int32_t)ci;
+            res.stage = r.stage;
+            res.k = r.k;
+            res.metric = r.metric;
+            std::memcpy(res.cw, r.cw, sizeof res.cw);
+            res.t_submit = c.slot_t[r.slot];
+            res.t_done = t;
+            s->done.push_back(res);
+            c.free_slots.push_back(r.slot);
+            --c.in_slots;
+        }
+    }
+    tb.busy = false;
+}
+
+int enqueue_tick(mpwsd_server* s, TickBuf& tb)
+{
+    hipStream_t st = s->stream;
+    for (size_t ci = 0; ci < s->codes.size(); ++ci) {
+        Code& c = s->codes[ci];
+        TickBuf::PerCode& p = tb.pc[ci];
+        const int n_new = (int)std::min(c.waiting.size(), c.free_slots.size());
+        for (int i = 0; i < n_new; ++i) {
+            Pending& w = c.waiting.front();
+            const int slot = c.free_slots.back();
+            c.free_slots.pop_back();
+            std::memcpy(p.y + (size_t)i * c.N, w.y.data(), sizeof(float) * c.N);
+            p.scale[i] = w.scale;
+            p.slot[i] = slot;
+            c.slot_tag[slot] = w.tag;
+            c.slot_t[slot] = w.t_submit;
+            c.waiting.pop_front();
+        }
+        c.in_slots += n_new;
+        p.maxrec = c.in_slots;
+        if (c.in_slots == 0) {
+            p.hdr[H_CCOUNT] = 0;
+            continue;
+        }
+        const int L = c.c.L, nxt = c.cur ^ 1;
+        int32_t* hdr = c.at<int32_t>(c.lay.hdr);
+        int32_t* act[2] = {c.at<int32_t>(c.lay.act0), c.at<int32_t>(c.lay.act1)};
+        hipLaunchKernelGGL(srv_prep_kernel, dim3(1), dim3(64), 0, st, hdr, nxt);
+        if (n_new > 0) {
+            (void)hipMemcpyAsync(c.at<float>(c.lay.yst), p.y, sizeof(float) * c.N * n_new, hipMemcpyHostToDevice, st);
+            (void)hipMemcpyAsync(c.at<float>(c.lay.sst), p.scale, sizeof(float) * n_new, hipMemcpyHostToDevice, st);
+            (void)hipMemcpyAsync(c.at<int32_t>(c.lay.newslot), p.slot, sizeof(int32_t) * n_new, hipMemcpyHostToDevice,
+                                 st);
+            const int64_t tot = (int64_t)n_new * c.N;
+            hipLaunchKernelGGL(srv_quantize_kernel, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
+                               dim3(256), 0, st, c.at<float>(c.lay.yst), c.at<float>(c.lay.sst), n_new, c.N,
+                               c.at<int8_t>(c.lay.qst), hdr);
+            int rc = mpwsd_stage1_scl(c.c.r, c.c.m, c.c.crc_len, c.c.crc_poly, L, c.at<int8_t>(c.lay.qst), MPWSD_I8,
+                                      n_new, c.at<uint8_t>(c.lay.ancst), c.at<uint8_t>(c.lay.okst), nullptr, st);
+            if (rc != MPWSD_OK) return rc;
+            const int64_t work = (int64_t)n_new * L;
+            hipLaunchKernelGGL(srv_enter_kernel, dim3((unsigned)std::min<int64_t>((work + 255) / 256, 4096)),
+                               dim3(256), 0, st, n_new, L, c.N, c.KP, c.at<int8_t>(c.lay.qst),
+                               c.at<uint8_t>(c.lay.ancst), c.at<uint8_t>(c.lay.okst), c.at<int32_t>(c.lay.newslot),
+                               c.at<uint8_t>(c.lay.cw), c.at<int8_t>(c.lay.zneg), c.at<int32_t>(c.lay.metric),
+                               c.at<int32_t>(c.lay.citer), c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.fdone),
+                               act[c.cur], hdr, c.cur, c.at<Record>(c.lay.rec));
+        }
+        // one stage-2 iteration over every active path of this code
+        mpwsd::launch_search_i8(c.N, c.at<int8_t>(c.lay.zneg), c.c.moves, c.c.P, act[c.cur],
+                                hdr + (c.cur ? H_CNT1 : H_CNT0), c.at<long long>(c.lay.key), -1, 0, st);
+        const int cols = c.c.capacity * L;
+        hipLaunchKernelGGL(srv_resolve_kernel, dim3((unsigned)std::min(((cols + 255) / 256), 2048)), dim3(256), 0,
+                           st, L, c.c.T, c.N, c.KP, c.c.P, c.c.moves, c.at<uint8_t>(c.lay.cw),
+                           c.at<int8_t>(c.lay.zneg), c.at<int32_t>(c.lay.metric), c.at<int32_t>(c.lay.citer),
+                           c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.fdone), act[c.cur], act[nxt], hdr, c.cur,
+                           c.at<Record>(c.lay.rec));
+        (void)hipMemcpyAsync(p.hdr, hdr, sizeof(int32_t) * H_WORDS, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync(p.rec, c.at<Record>(c.lay.rec), sizeof(Record) * p.maxrec, hipMemcpyDeviceToHost, st);
+        c.cur = nxt;
+    }
+    hipError_t e = hipEventRecord(tb.ev, st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_server_tick: %s", hipGetErrorString(e));
+    tb.busy = true;
+    return MPWSD_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mpwsd_server_arena_bytes(const mpwsd_server_code* codes, int ncodes)
+{
+    mpwsd::clear_error();
+    if (check_codes(codes, ncodes) != MPWSD_OK) return 0;
+    size_t t = 0;
+    for (int i = 0; i < ncodes; ++i) t += layout(codes[i]).bytes;
+    return t;
+}
+
+extern "C" int mpwsd_server_create(const mpwsd_server_code* codes, int ncodes, void* arena, size_t arena_bytes,
+                                   mpwsd_server** out)
+{
+    using mpwsd::fail;
+    mpwsd::clear_error();
+    int rc = check_codes(codes, ncodes);
+    if (rc != MPWSD_OK) return rc;
+    if (!out) return fail(MPWSD_ERR_ARG, "mpwsd_server_create: out is NULL");
+    size_t need = 0;
+    for (int i = 0; i < ncodes; ++i) need += layout(codes[i]).bytes;
+    if (!arena || arena_bytes < need)
+        return fail(MPWSD_ERR_SIZE, "mpwsd_server_create: arena needs %zu bytes, got %zu", need, arena_bytes);
+    if ((reinterpret_cast<uintptr_t>(arena) & 255u) != 0)
+        return fail(MPWSD_ERR_ARG, "mpwsd_server_create: arena must be 256-byte aligned");
+    auto* s = new mpwsd_server();
+    hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+    uint8_t* base = (uint8_t*)arena;
+    for (int i = 0; i < ncodes && e == hipSuccess; ++i) {
+        Code c;
+        c.c = codes[i];
+        c.N = 1 << codes[i].m;
+        c.KP = c.N < 64 ? 64 : c.N;
+        c.NB = c.N / 8;
+        c.lay = layout(codes[i]);
+        c.base = base;
+        base += c.lay.bytes;
+        c.free_slots.resize(codes[i].capacity);
+        for (int k = 0; k < codes[i].capacity; ++k) c.free_slots[k] = codes[i].capacity - 1 - k;
+        c.slot_tag.assign(codes[i].capacity, 0);
+        c.slot_t.assign(codes[i].capacity, 0.0);
+        s->codes.push_back(std::move(c));
+    }
+    for (auto& tb : s->ticks) {
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&tb.ev, hipEventDisableTiming);
+        tb.pc.resize(ncodes);
+        for (int i = 0; i < ncodes && e == hipSuccess; ++i) {
+            const Code& c = s->codes[i];
+            const size_t C = (size_t)c.c.capacity;
+            auto& p = tb.pc[i];
+            e = hipHostMalloc((void**)&p.y, C * c.N * sizeof(float), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p.scale, C * sizeof(float), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p.slot, C * sizeof(int32_t), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p.hdr, H_WORDS * sizeof(int32_t), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p.rec, C * sizeof(Record), hipHostMallocDefault);
+        }
+    }
+    // zero the per-code headers (counts) with a kernel, not a memset node
+    for (auto& c : s->codes)
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(srv_prep_kernel, dim3(1), dim3(64), 0, s->stream, c.at<int32_t>(c.lay.hdr), 0);
+            hipLaunchKernelGGL(srv_prep_kernel, dim3(1), dim3(64), 0, s->stream, c.at<int32_t>(c.lay.hdr), 1);
+            e = hipGetLastError();
+        }
+    if (e != hipSuccess) {
+        int r = fail(MPWSD_ERR_DEVICE, "mpwsd_server_create: %s", hipGetErrorString(e));
+        mpwsd_server_destroy(s);
+        return r;
+    }
+    *out = s;
+    return MPWSD_OK;
+}
+
+extern "C" int mpwsd_server_submit(mpwsd_server* s, int code, int n, const float* y, const float* scale,
+                                   const uint64_t* tags)
+{
+    using mpwsd::fail;
+    mpwsd::clear_error();
+    if (!s || code < 0 || code >= (int)s->codes.size() || n < 0 || (n > 0 && (!y || !scale || !tags)))
+        return fail(MPWSD_ERR_ARG, "mpwsd_server_submit: bad arguments");
+    Code& c = s->codes[code];
+    const double t = now_s();
+    for (int i = 0; i < n; ++i) {
+        Pending p;
+        p.tag = tags[i];
+        p.scale = scale[i];
+        p.t_submit = t;
+        p.y.assign(y + (size_t)i * c.N, y + (size_t)(i + 1) * c.N);
+        c.waiting.push_back(std::move(p));
+    }
+    s->submitted += n;
+    return MPWSD_OK;
+}
+
+extern "C" int mpwsd_server_tick(mpwsd_server* s, int64_t* in_flight)
+{
+    mpwsd::clear_error();
+    if (!s) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_server_tick: server is NULL");
+    // harvest finished ticks in order
+    for (int k = 0; k < 2; ++k) {
+        TickBuf& tb = s->ticks[(s->next_tick + k) & 1];
+        if (tb.busy && hipEventQuery(tb.ev) == hipSuccess) harvest(s, tb);
+    }
+    bool work = false;
+    for (auto& c : s->codes) work = work || c.in_slots > 0 || !c.waiting.empty();
+    if (work) {
+        TickBuf& tb = s->ticks[s->next_tick];
+        if (tb.busy) {  // both in flight: wait for the older one
+            (void)hipEventSynchronize(tb.ev);
+            harvest(s, tb);
+        }
+        int rc = enqueue_tick(s, tb);
+        if (rc != MPWSD_OK) return rc;
+        s->next_tick ^= 1;
+    }
+    if (in_flight) *in_flight = s->submitted - s->returned;
+    return MPWSD_OK;
+}
+
+extern "C" int mpwsd_server_poll(mpwsd_server* s, mpwsd_result* out, int cap)
+{
+    mpwsd::clear_error();
+    if (!s || cap < 0 || (cap > 0 && !out)) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_server_poll: bad arguments");
+    int n = 0;
+    while (n < cap && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    s->returned += n;
+    return n;
+}
+
+extern "C" int mpwsd_server_destroy(mpwsd_server* s)
+{
+    mpwsd::clear_error();
+    if (!s) return MPWSD_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (auto& tb : s->ticks) {
+        if (tb.ev) (void)hipEventDestroy(tb.ev);
+        for (auto& p : tb.pc) {
+            if (p.y) (void)hipHostFree(p.y);
+            if (p.scale) (void)hipHostFree(p.scale);
+            if (p.slot) (void)hipHostFree(p.slot);
+            if (p.hdr) (void)hipHostFree(p.hdr);
+            if (p.rec) (void)hipHostFree(p.rec);
+        }
+    }
+    if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return MPWSD_OK;
+}
+
+extern "C" int mpwsd_serve_trace(mpwsd_server* s, int64_t n, const int32_t* code, const int64_t* row,
+                                 const float* scale, const double* arrival, const float* const* pools,
+                                 mpwsd_result* out)
+{
+    using mpwsd::fail;
+    mpwsd::clear_error();
+    if (!s || n < 0 || (n > 0 && (!code || !row || !scale || !arrival || !pools || !out)))
+        return fail(MPWSD_ERR_ARG, "mpwsd_serve_trace: bad arguments");
+    for (int64_t i = 0; i < n; ++i)
+        if (code[i] < 0 || code[i] >= (int)s->codes.size() || !pools[code[i]] || row[i] < 0)
+            return fail(MPWSD_ERR_ARG, "mpwsd_serve_trace: bad trace entry %lld", (long long)i);
+    const double t0 = now_s();
+    int64_t next = 0, got = 0;
+    std::vector<mpwsd_result> buf(4096);
+    while (got < n) {
+        const double t = now_s() - t0;
+        while (next < n && arrival[next] <= t) {
+            const int c = code[next];
+            const uint64_t tag = (uint64_t)next;
+            const int rc = mpwsd_server_submit(s, c, 1, pools[c] + (size_t)row[next] * s->codes[c].N, &scale[next], &tag);
+            if (rc != MPWSD_OK) return rc;
+            ++next;
+        }
+        int64_t inflight = 0;
+        int rc = mpwsd_server_tick(s, &inflight);
+        if (rc != MPWSD_OK) return rc;
+        int k;
+        while ((k = mpwsd_server_poll(s, buf.data(), (int)buf.size())) > 0) {
+            for (int i = 0; i < k; ++i) {
+                const int64_t tag = (int64_t)buf[i].tag;
+                if (tag >= 0 && tag < n) out[tag] = buf[i];
+            }
+            got += k;
+        }
+        if (inflight == 0 && next < n) {
+            // idle until the next arrival
+            const double wait = arrival[next] - (now_s() - t0);
+            if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 1e-4));
+        }
+    }
+    return MPWSD_OK;
+}

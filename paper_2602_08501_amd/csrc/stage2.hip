@@ -262,7 +262,7 @@ __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
 template <int N, int NC, int NWAVES, int BPC>
 __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
     const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
-    const int32_t* __restrict__ act, const int32_t* __restrict__ hdr, int t, long long* __restrict__ keys)
+    const int32_t* __restrict__ act, const int32_t* __restrict__ count, long long* __restrict__ keys)
 {
     constexpr int KP = N < 64 ? 64 : N;         // K padded to the MFMA depth
     constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
     constexpr int NT = NWAVES * WAVE;
     __shared__ __attribute__((aligned(16))) int8_t lds[2][RC * RS];
 
-    const int n = hdr[2 + t];
+    const int n = *count;
     if (n <= 0) return;
     constexpr int NB = N / 8;                   // packed bytes per move
     constexpr int UW = N / 32;                  // 32-bit units per move
@@ -647,22 +647,24 @@ constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 int default_variant(int N) { return N >= 256 ? 1 : 0; }
 
 template <int N, int V>
-void launch_search_i8_v(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
+void launch_search_i8_v(const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
+                        const int32_t* count, long long* keys, hipStream_t s, int grid)
 {
     constexpr Variant v = kVariants[V];
-    hipLaunchKernelGGL((search_i8_kernel<N, v.nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s,
-                       (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, (long long*)w.key64);
+    hipLaunchKernelGGL((search_i8_kernel<N, v.nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s, zneg, moves, P,
+                       act, count, keys);
 }
 
 template <int N>
-void launch_search_i8(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int variant, int grid)
+void launch_search_i8_n(const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
+                        const int32_t* count, long long* keys, hipStream_t s, int variant, int grid)
 {
     switch (variant) {
-    case 0: launch_search_i8_v<N, 0>(w, sg, t, s, grid); break;
-    case 1: launch_search_i8_v<N, 1>(w, sg, t, s, grid); break;
-    case 2: launch_search_i8_v<N, 2>(w, sg, t, s, grid); break;
-    case 3: launch_search_i8_v<N, 3>(w, sg, t, s, grid); break;
-    default: launch_search_i8_v<N, 4>(w, sg, t, s, grid); break;
+    case 0: launch_search_i8_v<N, 0>(zneg, moves, P, act, count, keys, s, grid); break;
+    case 1: launch_search_i8_v<N, 1>(zneg, moves, P, act, count, keys, s, grid); break;
+    case 2: launch_search_i8_v<N, 2>(zneg, moves, P, act, count, keys, s, grid); break;
+    case 3: launch_search_i8_v<N, 3>(zneg, moves, P, act, count, keys, s, grid); break;
+    default: launch_search_i8_v<N, 4>(zneg, moves, P, act, count, keys, s, grid); break;
     }
 }
 
@@ -710,17 +712,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
                                N, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
                                (unsigned long long*)w.key64, w.fid, L, sg.out_moves);
         } else {
-            const int var = variant >= 0 ? variant : default_variant(N);
-            // workgroups per CU: requested, else the variant's default capped
-            // by how many fit in the 160 KB LDS of a CU
-            const int lds_fit = (160 * 1024) / (2 * RC * (KP + 16));
-            const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
-            switch (N) {
-            case 32: launch_search_i8<32>(w, sg, t, s, var, grid); break;
-            case 64: launch_search_i8<64>(w, sg, t, s, var, grid); break;
-            case 128: launch_search_i8<128>(w, sg, t, s, var, grid); break;
-            default: launch_search_i8<256>(w, sg, t, s, var, grid); break;
-            }
+            mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr + 2 + t,
+                                    (long long*)w.key64, variant, blocks_per_cu, s);
             if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
             hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
                                sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (long long*)w.key64, w.fid,
@@ -768,6 +761,28 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
 }
 
 }  // namespace
+
+namespace mpwsd {
+int device_cu_count() { return device_cus(); }
+
+void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
+                      const int32_t* count, long long* keys, int variant, int blocks_per_cu, hipStream_t s)
+{
+    const int cus = device_cus();
+    const int KP = kpad(N);
+    const int var = variant >= 0 ? variant : default_variant(N);
+    // workgroups per CU: requested, else the variant's default capped by how
+    // many fit in the 160 KB LDS of a CU
+    const int lds_fit = (160 * 1024) / (2 * RC * (KP + 16));
+    const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
+    switch (N) {
+    case 32: launch_search_i8_n<32>(zneg, moves, P, act, count, keys, s, var, grid); break;
+    case 64: launch_search_i8_n<64>(zneg, moves, P, act, count, keys, s, var, grid); break;
+    case 128: launch_search_i8_n<128>(zneg, moves, P, act, count, keys, s, var, grid); break;
+    default: launch_search_i8_n<256>(zneg, moves, P, act, count, keys, s, var, grid); break;
+    }
+}
+}  // namespace mpwsd
 
 extern "C" size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T)
 {

@@ -166,6 +166,29 @@ def generate(wl: Workload, seed: int, f0: int, f1: int):
     return payload, c, y
 
 
+def generate_snr_mix(wl: Workload, seed: int, f0: int, f1: int, ebn0_lo: float, ebn0_hi: float):
+    """Frames [f0, f1) whose Eb/N0 is drawn per frame uniformly in
+    [ebn0_lo, ebn0_hi] (from the frame's own stream).  Returns (payload,
+    codeword, y float32, per-frame Eb/N0, per-frame quantizer scale 8/sigma^2
+    as float32)."""
+    frames = np.arange(f0, f1, dtype=np.uint64)
+    F, n = len(frames), wl.N
+    kp = stream_keys(seed, wl.wid, wl.snr_index, frames, 0)
+    payload = (stream(kp, wl.k_pay) >> np.uint64(63)).astype(np.uint8)
+    v = crc_append(payload, wl.crc_len, wl.crc_poly)
+    A = info_positions(wl.r, wl.m)
+    u = np.zeros((F, n), np.uint8)
+    u[:, A] = v
+    c = polar_transform(u, wl.m)
+    ks = stream_keys(seed, wl.wid, wl.snr_index, frames, 2)
+    ebn0 = ebn0_lo + (ebn0_hi - ebn0_lo) * uniform53(stream(ks, 1)[:, 0])
+    sigma2 = 1.0 / (2.0 * wl.rate * 10.0 ** (ebn0 / 10.0))
+    kn = stream_keys(seed, wl.wid, wl.snr_index, frames, 1)
+    noise = gaussian(kn, n) * np.sqrt(sigma2)[:, None]
+    y = ((1.0 - 2.0 * c.astype(np.float64)) + noise).astype(np.float32)
+    return payload, c, y, ebn0, (8.0 / sigma2).astype(np.float32)
+
+
 # The workloads the decoder is measured on (codes, payloads and SNR grids).
 RM26 = Workload(r=2, m=6, k_pay=16, ebn0_db=3.0, wid=0)
 RM37 = Workload(r=3, m=7, k_pay=58, ebn0_db=2.5, wid=1)

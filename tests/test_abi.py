@@ -17,7 +17,9 @@ def test_library_exports_every_declared_call():
     assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_quantize_llr",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
-                          "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy"}
+                          "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy",
+                          "mpwsd_server_arena_bytes", "mpwsd_server_create", "mpwsd_server_submit",
+                          "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"}
     for n in names:
         assert hasattr(lib, n), n
 
@@ -127,3 +129,25 @@ def test_search_variants_and_option_errors():
     assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, blocks_per_cu=-1) == _lib.MPWSD_ERR_ARG
     assert _lib.load().mpwsd_graph_launch(None, None) == _lib.MPWSD_ERR_ARG
     assert _lib.load().mpwsd_graph_destroy(None) == 0
+
+
+def test_server_argument_errors():
+    from paper_2602_08501_amd._lib import ServerCode
+    import ctypes
+    lib = _lib.load()
+    good = ServerCode(3, 7, 0x1000, 94488, 8, 8, 6, 0x43, 64)
+    arr = (ServerCode * 1)(good)
+    assert lib.mpwsd_server_arena_bytes(arr, 1) > 0
+    for bad in (ServerCode(3, 7, 0x1000, 8128, 8, 8, 6, 0x43, 64), ServerCode(3, 9, 0x1000, 94488, 8, 8, 6, 0x43, 64),
+                ServerCode(3, 7, 0x1000, 94488, 6, 8, 6, 0x43, 64), ServerCode(3, 7, 0x1000, 94488, 8, 8, 6, 0x43, 0),
+                ServerCode(3, 7, None, 94488, 8, 8, 6, 0x43, 64)):
+        a = (ServerCode * 1)(bad)
+        assert lib.mpwsd_server_arena_bytes(a, 1) == 0
+        h = ctypes.c_void_p()
+        assert lib.mpwsd_server_create(a, 1, 0x10000, 1 << 40, ctypes.byref(h)) < 0
+    h = ctypes.c_void_p()
+    need = lib.mpwsd_server_arena_bytes(arr, 1)
+    assert lib.mpwsd_server_create(arr, 1, 0x10000, need - 1, ctypes.byref(h)) == _lib.MPWSD_ERR_SIZE
+    assert lib.mpwsd_server_create(arr, 1, 0x10010, need, ctypes.byref(h)) == _lib.MPWSD_ERR_ARG
+    assert lib.mpwsd_server_tick(None, None) == _lib.MPWSD_ERR_ARG
+    assert lib.mpwsd_server_destroy(None) == 0
