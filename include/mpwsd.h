@@ -161,6 +161,10 @@ size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T);
  * mode S_p is summed in binary32 in ascending j and the final metric is
  * ||y - x(c)||^2 summed in binary32 in ascending j.
  *
+ * Several int8 segments (up to 4, e.g. codes of different lengths) are
+ * decoded together: each iteration searches the failing paths of all of them
+ * in ONE launch of the search kernel.
+ *
  * segs[nseg]: host array.  All segments must use the same dtype.
  * ws: device workspace of ws_bytes >= mpwsd_workspace_bytes(...) bytes.
  * stats: device out int32[2 + T] or NULL: [0] = frames sent to stage 2
@@ -195,7 +199,9 @@ typedef struct mpwsd_options {
                             events[2 (s T + t)] is recorded right before and
                             events[2 (s T + t) + 1] right after the search
                             kernel of iteration t of segment s, on the same
-                            stream, for timing with hipEventElapsedTime */
+                            stream, for timing with hipEventElapsedTime; when
+                            several int8 segments share one search launch,
+                            only events[2 t] and events[2 t + 1] are recorded */
 } mpwsd_options;
 
 /*

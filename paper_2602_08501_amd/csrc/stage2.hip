@@ -259,36 +259,32 @@ __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
     }
 }
 
-template <int N, int NC, int NWAVES, int BPC>
-__global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
-    const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
-    const int32_t* __restrict__ act, const int32_t* __restrict__ count, long long* __restrict__ keys)
+// The sweep of one column tile of one code over move chunks [c0, c1): every
+// wave keeps its columns' -z fragments in VGPRs, the workgroup stages the
+// chunks through LDS, and each column's lexicographic (S, p) minimum over the
+// range is folded into keys[column] with one atomicMin.
+template <int N, int NC, int NWAVES>
+__device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_t* __restrict__ z,
+                                           const uint8_t* __restrict__ moves, int64_t P,
+                                           const int32_t* __restrict__ act, int n, long long* __restrict__ keys,
+                                           int tile, int c0, int c1)
 {
     constexpr int KP = N < 64 ? 64 : N;         // K padded to the MFMA depth
     constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
     constexpr int CT = NWAVES * 16 * NC;        // columns per tile
     constexpr int HK = KP / 64;                 // MFMAs per 16 x 16 output tile
     constexpr int NT = NWAVES * WAVE;
-    __shared__ __attribute__((aligned(16))) int8_t lds[2][RC * RS];
-
-    const int n = *count;
-    if (n <= 0) return;
     constexpr int NB = N / 8;                   // packed bytes per move
     constexpr int UW = N / 32;                  // 32-bit units per move
-    const int tiles = (n + CT - 1) / CT;
-    const int C = (int)((P + RC - 1) / RC);
-    const int64_t U = (int64_t)tiles * C;
-    int64_t u0 = U * blockIdx.x / gridDim.x;
-    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
-    if (u0 >= u1) return;
+    int8_t* buf[2] = {lds, lds + RC * RS};
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const v4i seed0 = {4 * lg, 4 * lg + 1, 4 * lg + 2, 4 * lg + 3};
 
-    if (N < KP) {  // positions >= N stay zero for the whole launch
+    if (N < KP) {  // positions >= N stay zero
         for (int e = tid; e < 2 * RC; e += NT) {
-            int8_t* row = &lds[e / RC][(e % RC) * RS];
+            int8_t* row = buf[e / RC] + (e % RC) * RS;
             for (int j = N; j < KP; j += 16) *(v4i*)(row + j) = v4i{0, 0, 0, 0};
         }
     }
@@ -316,96 +312,170 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
                 const int row = u / UW, wd = u % UW;
                 uint32_t o[8];
                 unpack32(reg[r], o);
-                int8_t* dst = &lds[b][row * RS + 32 * wd];
+                int8_t* dst = buf[b] + row * RS + 32 * wd;
                 *(v4i*)(dst) = v4i{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
                 *(v4i*)(dst + 16) = v4i{(int)o[4], (int)o[5], (int)o[6], (int)o[7]};
             }
         }
     };
 
+    // -z fragments of this wave's columns; they stay in VGPRs for the sweep
+    v4i zf[NC][HK];
+    int colid[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int pos = tile * CT + wave * 16 * NC + c * 16 + li;
+        colid[c] = pos < n ? act[pos] : -1;
+#pragma unroll
+        for (int h = 0; h < HK; ++h) {
+            if (colid[c] >= 0)
+                zf[c][h] = *(const v4i*)(z + (size_t)colid[c] * KP + lg * (KP / 4) + 16 * h);
+            else
+                zf[c][h] = v4i{0, 0, 0, 0};
+        }
+    }
+    // Chunks are swept in decreasing order, so a chunk replaces the running
+    // best when its minimum S is <= the best S (ties go to the lower chunk);
+    // within a chunk D = 128 S + row orders by (S, row).
+    int run[NC], runk[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) { run[c] = INT_MAX; runk[c] = 0; }
+
+    uint32_t reg[UR];
+    fetch(c1 - 1, reg);
+    store(0, reg);
+    __syncthreads();
+    for (int k = c1 - 1; k >= c0; --k) {
+        const int b = (c1 - 1 - k) & 1;
+        if (k > c0) fetch(k - 1, reg);
+        int cm[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) cm[c] = INT_MAX;
+#pragma unroll 2
+        for (int tt = 0; tt < RC / 16; ++tt) {
+            v4i af[HK];
+            const int8_t* src = buf[b] + (tt * 16 + li) * RS + lg * (KP / 4);
+#pragma unroll
+            for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
+            // accumulator seed: the row's index within the chunk
+            const v4i seed = seed0 + v4i{16 * tt, 16 * tt, 16 * tt, 16 * tt};
+            // all column blocks' MFMAs back to back into separate
+            // accumulators, so the matrix pipe never waits on the epilogue
+            v4i acc[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[0], zf[c][0], seed, 0, 0, 0);
+#pragma unroll
+            for (int h = 1; h < HK; ++h)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc[c], 0, 0, 0);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {  // two v_min3 per four values
+                const int t3 = min(min(acc[c][0], acc[c][1]), acc[c][2]);
+                cm[c] = min(min(cm[c], t3), acc[c][3]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const bool take = cm[c] <= (run[c] | 127);  // S(cm) <= S(run)
+            run[c] = take ? cm[c] : run[c];
+            runk[c] = take ? k : runk[c];
+        }
+        if (k > c0) store(b ^ 1, reg);
+        __syncthreads();
+    }
+    // lanes li, li+16, li+32, li+48 hold the same column
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        long long v = ((long long)(run[c] >> 7) << 32) | (long long)(uint32_t)((runk[c] << 7) | (run[c] & 127));
+        long long o = __shfl_xor(v, 16);
+        v = o < v ? o : v;
+        o = __shfl_xor(v, 32);
+        v = o < v ? o : v;
+        if (lg == 0 && colid[c] >= 0) atomicMin(&keys[colid[c]], v);
+    }
+}
+
+// One code: (column tile x move chunk) units spread evenly over the grid.
+template <int N, int NC, int NWAVES, int BPC>
+__global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
+    const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
+    const int32_t* __restrict__ act, const int32_t* __restrict__ count, long long* __restrict__ keys)
+{
+    constexpr int KP = N < 64 ? 64 : N;
+    constexpr int CT = NWAVES * 16 * NC;
+    __shared__ __attribute__((aligned(16))) int8_t lds[2 * RC * (KP + 16)];
+    const int n = *count;
+    if (n <= 0) return;
+    const int tiles = (n + CT - 1) / CT;
+    const int C = (int)((P + RC - 1) / RC);
+    const int64_t U = (int64_t)tiles * C;
+    int64_t u0 = U * blockIdx.x / gridDim.x;
+    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
     while (u0 < u1) {
         const int tile = (int)(u0 / C);
         const int c0 = (int)(u0 % C);
         const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
         u0 += c1 - c0;
+        sweep_tile<N, NC, NWAVES>(lds, z, moves, P, act, n, keys, tile, c0, c1);
+    }
+}
 
-        // z fragments of this wave's columns; they stay in VGPRs for the sweep
-        v4i zf[NC][HK];
-        int colid[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int pos = tile * CT + wave * 16 * NC + c * 16 + li;
-            colid[c] = pos < n ? act[pos] : -1;
-#pragma unroll
-            for (int h = 0; h < HK; ++h) {
-                if (colid[c] >= 0)
-                    zf[c][h] = *(const v4i*)(z + (size_t)colid[c] * KP + lg * (KP / 4) + 16 * h);
-                else
-                    zf[c][h] = v4i{0, 0, 0, 0};
-            }
-        }
-        // Chunks are swept in decreasing order, so a chunk replaces the
-        // running best when its minimum S is <= the best S (ties go to the
-        // lower chunk); within a chunk D = 128 S + row orders by (S, row).
-        int run[NC], runk[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) { run[c] = INT_MAX; runk[c] = 0; }
+// Several codes in one launch: the units of all segments are concatenated
+// and spread over one persistent grid; a workgroup's range may cross from one
+// code into the next.
+struct SegSearch {
+    const int8_t* z;
+    const uint8_t* moves;
+    int64_t P;
+    const int32_t* act;
+    const int32_t* count;
+    long long* keys;
+    int N;
+};
+constexpr int kMaxSeg = 4;
+struct MultiSearch {
+    SegSearch s[kMaxSeg];
+    int nseg;
+};
 
-        uint32_t reg[UR];
-        fetch(c1 - 1, reg);
-        store(0, reg);
-        __syncthreads();
-        for (int k = c1 - 1; k >= c0; --k) {
-            const int b = (c1 - 1 - k) & 1;
-            if (k > c0) fetch(k - 1, reg);
-            int cm[NC];
+template <int KPMAX, int NC, int NWAVES, int BPC>
+__global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(MultiSearch ms)
+{
+    constexpr int CT = NWAVES * 16 * NC;
+    __shared__ __attribute__((aligned(16))) int8_t lds[2 * RC * (KPMAX + 16)];
+    int64_t ustart[kMaxSeg + 1];
+    int nn[kMaxSeg], cc[kMaxSeg];
+    ustart[0] = 0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) cm[c] = INT_MAX;
-#pragma unroll 2
-            for (int tt = 0; tt < RC / 16; ++tt) {
-                v4i af[HK];
-                const int8_t* src = &lds[b][(tt * 16 + li) * RS + lg * (KP / 4)];
+    for (int i = 0; i < kMaxSeg; ++i) {
+        const bool on = i < ms.nseg;
+        nn[i] = on ? *ms.s[i].count : 0;
+        cc[i] = on ? (int)((ms.s[i].P + RC - 1) / RC) : 1;
+        const int tiles = (nn[i] + CT - 1) / CT;
+        ustart[i + 1] = ustart[i] + (int64_t)tiles * cc[i];
+    }
+    const int64_t U = ustart[kMaxSeg];
+    int64_t u0 = U * blockIdx.x / gridDim.x;
+    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    while (u0 < u1) {
+        int si = 0;
 #pragma unroll
-                for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
-                // accumulator seed: the row's index within the chunk
-                const v4i seed = seed0 + v4i{16 * tt, 16 * tt, 16 * tt, 16 * tt};
-                // all column blocks' MFMAs back to back into separate
-                // accumulators, so the matrix pipe never waits on the epilogue
-                v4i acc[NC];
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[0], zf[c][0], seed, 0, 0, 0);
-#pragma unroll
-                for (int h = 1; h < HK; ++h)
-#pragma unroll
-                    for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc[c], 0, 0, 0);
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {  // two v_min3 per four values
-                    const int t3 = min(min(acc[c][0], acc[c][1]), acc[c][2]);
-                    cm[c] = min(min(cm[c], t3), acc[c][3]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const bool take = cm[c] <= (run[c] | 127);  // S(cm) <= S(run)
-                run[c] = take ? cm[c] : run[c];
-                runk[c] = take ? k : runk[c];
-            }
-            if (k > c0) store(b ^ 1, reg);
-            __syncthreads();
-        }
-        long long best[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            best[c] = ((long long)(run[c] >> 7) << 32) | (long long)(uint32_t)((runk[c] << 7) | (run[c] & 127));
-        // lanes li, li+16, li+32, li+48 hold the same column
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            long long v = best[c];
-            long long o = __shfl_xor(v, 16);
-            v = o < v ? o : v;
-            o = __shfl_xor(v, 32);
-            v = o < v ? o : v;
-            if (lg == 0 && colid[c] >= 0) atomicMin(&keys[colid[c]], v);
+        for (int i = 1; i < kMaxSeg; ++i) si = u0 >= ustart[i] ? i : si;
+        const SegSearch& sg = ms.s[si];
+        const int64_t local = u0 - ustart[si];
+        const int C = cc[si];
+        const int tile = (int)(local / C);
+        const int c0 = (int)(local % C);
+        const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
+        u0 += c1 - c0;
+        switch (sg.N) {
+        case 32: sweep_tile<32, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
+        case 64: sweep_tile<64, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
+        case 128: sweep_tile<128, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
+        default:
+            if constexpr (KPMAX >= 256)
+                sweep_tile<256, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1);
+            break;
         }
     }
 }
@@ -681,55 +751,137 @@ void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream
     }
 }
 
-int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipEvent_t* ev,
-                int variant, int blocks_per_cu, hipStream_t s)
+template <int KPMAX, int V>
+void launch_multi_v(const MultiSearch& ms, hipStream_t s, int grid)
+{
+    constexpr Variant v = kVariants[V];
+    hipLaunchKernelGGL((search_i8_multi_kernel<KPMAX, v.nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s, ms);
+}
+
+// variants 0..2 have a multi-code form; others fall back to the default
+void launch_search_multi(const MultiSearch& ms, int maxN, int variant, int blocks_per_cu, hipStream_t s)
+{
+    const int cus = device_cus();
+    const int kp = maxN <= 128 ? 128 : 256;
+    int var = (variant >= 0 && variant <= 2) ? variant : default_variant(maxN);
+    const int lds_fit = (160 * 1024) / (2 * RC * (kp + 16));
+    const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
+    if (kp == 128) {
+        switch (var) {
+        case 0: launch_multi_v<128, 0>(ms, s, grid); break;
+        case 1: launch_multi_v<128, 1>(ms, s, grid); break;
+        default: launch_multi_v<128, 2>(ms, s, grid); break;
+        }
+    } else {
+        switch (var) {
+        case 0: launch_multi_v<256, 1>(ms, s, grid); break;  // NC = 8 does not fit N = 256 registers
+        case 1: launch_multi_v<256, 1>(ms, s, grid); break;
+        default: launch_multi_v<256, 2>(ms, s, grid); break;
+        }
+    }
+}
+
+// Phases of stage 2 for one segment.
+void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipStream_t s)
 {
     const int N = 1 << sg.m, KP = kpad(N);
     const bool fl = sg.dtype == MPWSD_F32;
-    const int cus = device_cus();
     hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(64), 0, s, w.hdr, 4 + T);
     hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((sg.F + 255) / 256)), dim3(256), 0, s, sg.crc_ok, sg.F, w.hdr,
                        w.fid, w.slot);
-    {
-        const int64_t work = sg.F * L * (KP / 16);
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
-        if (fl)
-            hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
-                               w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
-                               sg.out_metric, sg.out_moves, stats);
-        else
-            hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N,
-                               KP, w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw,
-                               sg.out_k, sg.out_metric, sg.out_moves, stats);
-    }
-    const int resolve_blocks = cus * 4;
+    const int64_t work = sg.F * L * (KP / 16);
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
+    if (fl)
+        hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
+                           w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           sg.out_metric, sg.out_moves, stats);
+    else
+        hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
+                           w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           sg.out_metric, sg.out_moves, stats);
+}
+
+void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, hipStream_t s)
+{
+    const int N = 1 << sg.m, KP = kpad(N);
+    const int resolve_blocks = device_cus() * 4;
+    if (sg.dtype == MPWSD_F32)
+        hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves, N,
+                           sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (unsigned long long*)w.key64, w.fid,
+                           L, sg.out_moves);
+    else
+        hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
+                           sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
+                           (long long*)w.key64, w.fid, L, sg.out_moves);
+}
+
+void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipStream_t s)
+{
+    const int N = 1 << sg.m;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
+    if (sg.dtype == MPWSD_F32)
+        hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N, w.metric,
+                           w.cw, sg.out_cw, sg.out_k, sg.out_metric);
+    else
+        hipLaunchKernelGGL(select_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
+                           w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
+    if (stats) hipLaunchKernelGGL(stats_add_kernel, dim3(1), dim3(128), 0, s, w.hdr, T, stats);
+}
+
+int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipEvent_t* ev,
+                int variant, int blocks_per_cu, hipStream_t s)
+{
+    const int N = 1 << sg.m;
+    seg_prologue(sg, L, T, w, stats, s);
     for (int t = 0; t < T; ++t) {
         if (ev) (void)hipEventRecord(ev[2 * t], s);
-        if (fl) {
-            launch_search_f32(w, sg, t, s, cus * 4);
-            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
-            hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves,
-                               N, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
-                               (unsigned long long*)w.key64, w.fid, L, sg.out_moves);
-        } else {
+        if (sg.dtype == MPWSD_F32)
+            launch_search_f32(w, sg, t, s, device_cus() * 4);
+        else
             mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr + 2 + t,
                                     (long long*)w.key64, variant, blocks_per_cu, s);
-            if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
-            hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
-                               sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (long long*)w.key64, w.fid,
-                               L, sg.out_moves);
+        if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+        seg_resolve(sg, L, T, w, t, s);
+    }
+    seg_epilogue(sg, L, T, w, stats, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch: %s", hipGetErrorString(e));
+    return MPWSD_OK;
+}
+
+// Several int8 segments: every iteration's search of all codes is ONE launch.
+int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w, int32_t* stats, hipEvent_t* ev,
+              int variant, int blocks_per_cu, hipStream_t s)
+{
+    MultiSearch base{};
+    int maxN = 0;
+    for (int i = 0; i < nseg; ++i) {
+        if (segs[i].F == 0) continue;
+        seg_prologue(segs[i], L, T, w[i], stats, s);
+        SegSearch& g = base.s[base.nseg++];
+        g.z = (const int8_t*)w[i].z;
+        g.moves = segs[i].moves;
+        g.P = segs[i].P;
+        g.keys = (long long*)w[i].key64;
+        g.N = 1 << segs[i].m;
+        maxN = std::max(maxN, g.N);
+    }
+    for (int t = 0; t < T; ++t) {
+        MultiSearch ms = base;
+        for (int i = 0, j = 0; i < nseg; ++i) {
+            if (segs[i].F == 0) continue;
+            ms.s[j].act = w[i].act[t & 1];
+            ms.s[j].count = w[i].hdr + 2 + t;
+            ++j;
         }
+        if (ev) (void)hipEventRecord(ev[2 * t], s);
+        if (ms.nseg > 0) launch_search_multi(ms, maxN, variant, blocks_per_cu, s);
+        if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
+        for (int i = 0; i < nseg; ++i)
+            if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, s);
     }
-    {
-        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
-        if (fl)
-            hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
-                               w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
-        else
-            hipLaunchKernelGGL(select_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
-                               w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
-    }
-    if (stats) hipLaunchKernelGGL(stats_add_kernel, dim3(1), dim3(128), 0, s, w.hdr, T, stats);
+    for (int i = 0; i < nseg; ++i)
+        if (segs[i].F > 0) seg_epilogue(segs[i], L, T, w[i], stats, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch: %s", hipGetErrorString(e));
     return MPWSD_OK;
@@ -812,12 +964,18 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
         return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: workspace must be 256-byte aligned");
     if (stats) hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, stream, stats, 2 + T);
     uint8_t* base = (uint8_t*)ws;
+    std::vector<SegWs> w(nseg);
     for (int i = 0; i < nseg; ++i) {
-        SegWs w = carve(segs[i], L, T, base);
-        base += w.bytes;
+        w[i] = carve(segs[i], L, T, base);
+        base += w[i].bytes;
+    }
+    if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8)
+        return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr, variant,
+                         bpc, stream);
+    for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
         hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
-        rc = run_segment(segs[i], L, T, w, stats, ev, variant, bpc, stream);
+        rc = run_segment(segs[i], L, T, w[i], stats, ev, variant, bpc, stream);
         if (rc != MPWSD_OK) return rc;
     }
     return MPWSD_OK;
