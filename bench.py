@@ -3,9 +3,15 @@
 One step = the whole decoder over one batch resident in HBM: int8 LLR
 quantization, stage-1 SC-list decoding with the CRC test, compaction of the
 failing frames, T iterations of the stage-2 move search / apply, and the
-final choice.  Workload: RM(3,7) (N=128, K=64 = 58 payload + CRC-6), BPSK
-over AWGN at Eb/N0 = 2.5 dB, 65536 frames, int8 LLRs (scale 8/sigma^2),
+final choice.  The step is recorded once as a HIP graph and replayed.
+
+Default workload (the metric's): RM(3,7) (N=128, K=64 = 58 payload + CRC-6),
+BPSK over AWGN at Eb/N0 = 2.5 dB, 65536 frames, int8 LLRs (scale 8/sigma^2),
 L = 8 anchors, T = 8 iterations, 94488 moves (seeded synthetic data).
+Other workloads: --workload rm38 (RM(3,8), 32768 frames at 2.0 dB, L=16,
+T=12, 777240 moves) and --workload mixed (262144 frames, RM(2,6) / RM(2,7)
+/ RM(3,7) in equal shares at 2.5 dB, L=8, T=8, all codes' failing frames in
+one search launch per iteration).
 
 Prints one JSON line.  The roofline entry is for the stage-2 move-search
 kernel: dense int8 MFMA work 2 P N per searched path and iteration, over
@@ -28,7 +34,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MI355X_INT8_DENSE_TOPS = 5000.0  # AMD published dense int8 MFMA peak (TOP/s)
-MI355X_HBM_GBS = 8000.0
 
 
 def parse():
@@ -36,12 +41,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--frames", type=int, default=65536)
-    ap.add_argument("--ebn0", type=float, default=2.5)
-    ap.add_argument("--L", type=int, default=8)
-    ap.add_argument("--T", type=int, default=8)
+    ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed"])
+    ap.add_argument("--frames", type=int, default=0, help="override the workload's frame count")
+    ap.add_argument("--ebn0", type=float, default=None, help="override the workload's Eb/N0")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--cpu-frames", type=int, default=16384, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-frames", type=int, default=-1,
+                    help="oracle sample size in frames (0 = skip; default: the whole batch, 4096 for rm38)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a reference dispatch of "
@@ -49,24 +54,31 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(wl, y, L, T, nframes, threads):
-    import oracle
-    from paper_2602_08501_amd import synth  # noqa: F401
-    q = oracle.quantize(y[:nframes], wl.llr_scale).astype(np.float64)
-    oracle.moves(wl.r, wl.m)  # table built outside the timed region
-    t0 = time.perf_counter()
-    oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": nframes / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d frames of the same batch (int8 LLRs, full two-stage decode), %.1f s wall"
-                      % (nframes, dt)}
+def workload(args, synth):
+    """[(Workload, frames)], L, T."""
+    if args.workload == "rm37":
+        segs, L, T = [(synth.RM37, 65536)], 8, 8
+    elif args.workload == "rm38":
+        segs, L, T = [(synth.RM38, 32768)], 16, 12
+    else:
+        segs = [(dataclasses.replace(w, ebn0_db=2.5), f)
+                for w, f in ((synth.RM26, 87382), (synth.RM27, 87381), (synth.RM37, 87381))]
+        L, T = 8, 8
+    if args.ebn0 is not None:
+        segs = [(dataclasses.replace(w, ebn0_db=args.ebn0), f) for w, f in segs]
+    if args.frames:
+        segs = [(w, max(1, args.frames // len(segs))) for w, f in segs]
+    return segs, L, T
 
 
-def recorded_traffic():
+def recorded_traffic(workload_name):
     """HBM bytes per search launch from the committed counter summary, or None
-    when the kernel source changed since the counters were taken."""
+    when the kernel source changed since the counters were taken (or there is
+    no summary for this workload)."""
     import hashlib
     import re
+    if workload_name != "rm37":
+        return None
     path = os.path.join(ROOT, "profiles", "search_i8_rm37_65536f_hbm_traffic.txt")
     try:
         m = re.search(r"bench-traffic: source=(\S+) sha256=(\w+) hbm_bytes_per_launch=(\d+)", open(path).read())
@@ -78,9 +90,24 @@ def recorded_traffic():
     return int(m.group(3))
 
 
-def _lib_variants():
-    from paper_2602_08501_amd import _lib
-    return _lib.mpwsd_search_variants()
+def cpu_baseline(segs, ys, L, T, nframes, threads):
+    """The oracle on the first frames of every code's batch (the sample split
+    evenly over the codes), int8 arithmetic, whole two-stage decode."""
+    import oracle
+    qs, parts = [], []
+    for (wl, F), y in zip(segs, ys):
+        n = min(max(1, nframes // len(segs)), len(y))
+        qs.append(oracle.quantize(y[:n], wl.llr_scale).astype(np.float64))
+        oracle.moves(wl.r, wl.m)  # table built outside the timed region
+        parts.append("%d RM(%d,%d)" % (n, wl.r, wl.m))
+    t0 = time.perf_counter()
+    for (wl, F), q in zip(segs, qs):
+        oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads)
+    dt = time.perf_counter() - t0
+    n = sum(len(q) for q in qs)
+    return {"value": n / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
+            "sample": "first %s frames of the batch (int8 LLRs, full two-stage decode), %.1f s wall"
+                      % (" + ".join(parts), dt)}
 
 
 def main():
@@ -91,22 +118,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    from paper_2602_08501_amd import _lib, autotune
     from paper_2602_08501_amd import decoder as D
     from paper_2602_08501_amd import synth
 
-    wl = dataclasses.replace(synth.RM37, ebn0_db=args.ebn0)
-    F, L, T = args.frames, args.L, args.T
+    segs, L, T = workload(args, synth)
     dev = "cuda:0"
-    pay, c_tx, y = synth.generate(wl, args.seed, 0, F)
-    code = D.Code(wl.r, wl.m, dev)
-    y_d = torch.from_numpy(y).to(dev)
-    q_d = torch.empty(y.shape, dtype=torch.int8, device=dev)
-    s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
-          "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)}
-    st = D.Stage2([(code, F)], L, T, "i8", dev, want_moves=False)
     stream = torch.cuda.Stream()
-    scale = float(wl.llr_scale)
-    from paper_2602_08501_amd import autotune
     if args.calib_copy > 0:
         src = torch.ones(args.calib_copy << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -114,22 +132,44 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def step_eager(events=None, variant=-1, bpc=0):
-        D.quantize(y_d, scale, out=q_d, stream=stream)
-        D.stage1(code, L, q_d, wl.crc_len, wl.crc_poly, out=s1, stream=stream)
-        st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream, events=events, variant=variant,
-               blocks_per_cu=bpc)
+    codes, ys, txs, y_d, q_d, s1 = [], [], [], [], [], []
+    for wl, F in segs:
+        pay, c_tx, y = synth.generate(wl, args.seed, 0, F)
+        code = D.Code(wl.r, wl.m, dev)
+        codes.append(code)
+        ys.append(y)
+        txs.append(c_tx)
+        y_d.append(torch.from_numpy(y).to(dev))
+        q_d.append(torch.empty(y.shape, dtype=torch.int8, device=dev))
+        s1.append({"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
+                   "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)})
+    F_total = sum(F for _, F in segs)
+    st = D.Stage2([(c, F) for c, (_, F) in zip(codes, segs)], L, T, "i8", dev, want_moves=False)
+    nseg = len(segs)
+
+    def stage1_all(raw=None):
+        for i, (wl, F) in enumerate(segs):
+            if raw is None:
+                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], stream=stream)
+                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], stream=stream)
+            else:
+                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], raw_stream=raw)
+                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], raw_stream=raw)
+
+    def stage2(events=None, variant=-1, bpc=0, raw=None):
+        st.run(q_d, [s["anchors"] for s in s1], [s["crc_ok"] for s in s1], stream=None if raw else stream,
+               events=events, variant=variant, blocks_per_cu=bpc, raw_stream=raw)
 
     with torch.cuda.stream(stream):
-        step_eager()
+        stage1_all()
+        stage2()
         torch.cuda.synchronize()
-        variant, bpc = autotune.tune(st, [q_d], [s1["anchors"]], [s1["crc_ok"]], stream=stream)
+        variant, bpc = autotune.tune(st, q_d, [s["anchors"] for s in s1], [s["crc_ok"] for s in s1], stream=stream)
 
         # the whole step recorded once as a HIP graph, replayed per step
         def record(raw):
-            D.quantize(y_d, scale, out=q_d, raw_stream=raw)
-            D.stage1(code, L, q_d, wl.crc_len, wl.crc_poly, out=s1, raw_stream=raw)
-            st.run([q_d], [s1["anchors"]], [s1["crc_ok"]], variant=variant, blocks_per_cu=bpc, raw_stream=raw)
+            stage1_all(raw)
+            stage2(variant=variant, bpc=bpc, raw=raw)
 
         graph = D.Graph(record)
         for _ in range(args.warmup):
@@ -147,10 +187,11 @@ def main():
         ms = t_start.elapsed_time(t_end) / args.steps
 
         # the same steps launched one by one with HIP events around every
-        # search kernel (its launch durations for the roofline entry)
+        # search launch (its durations for the roofline entry)
+        nev = 2 * T * nseg
         evs = []
         for _ in range(args.steps):
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(nev)]
             for x in e:
                 x.record(stream)
             evs.append(e)
@@ -158,25 +199,36 @@ def main():
         e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e_start.record(stream)
         for k in range(args.steps):
-            step_eager(evs[k], variant, bpc)
+            stage1_all()
+            stage2(evs[k], variant, bpc)
         e_end.record(stream)
         torch.cuda.synchronize()
         ms_eager = e_start.elapsed_time(e_end) / args.steps
+
+    # searched paths per iteration and segment (deterministic per segment)
+    per_seg_cols = []
+    for i, (wl, F) in enumerate(segs if nseg > 1 else []):
+        one = D.Stage2([(codes[i], F)], L, T, "i8", dev, want_moves=False)
+        one.run([q_d[i]], [s1[i]["anchors"]], [s1[i]["crc_ok"]])
+        torch.cuda.synchronize()
+        per_seg_cols.append(one.stats.cpu().numpy()[1:1 + T].astype(np.int64))
     stats = st.stats.cpu().numpy()
-    cols = stats[1:1 + T].astype(np.int64)
-    dense_ops = 2.0 * code.P * code.N * cols  # per launch
-    search_ms = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
-                          for k in range(args.steps)])
-    launches = search_ms.mean(0)
+    if nseg == 1:
+        per_seg_cols = [stats[1:1 + T].astype(np.int64)]
+    dense_ops = sum(2.0 * c.P * c.N * cols for c, cols in zip(codes, per_seg_cols))  # per launch
+    launches = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
+                         for k in range(args.steps)]).mean(0)
     achieved = float(dense_ops.sum() / (launches.sum() * 1e-3) / 1e12)
-    out = st.outs[0]
-    cw = np.unpackbits(out["cw"].cpu().numpy(), axis=-1, bitorder="little")
-    fer = float((cw != c_tx).any(1).mean())
-    f2 = int(stats[0])
-    moves_evals = float(code.P * cols.sum())
+    fer = []
+    for i in range(nseg):
+        cw = np.unpackbits(st.outs[i]["cw"].cpu().numpy(), axis=-1, bitorder="little")
+        fer.append(float((cw != txs[i]).any(1).mean()))
+    move_evals = float(sum(c.P * cols.sum() for c, cols in zip(codes, per_seg_cols)))
+    names = ["RM(%d,%d) N=%d P=%d Eb/N0 %.2f dB %d frames" % (w.r, w.m, c.N, c.P, w.ebn0_db, F)
+             for (w, F), c in zip(segs, codes)]
     res = {
         "metric": "decoded frames/sec at FER parity; stage-2 move-evals/sec (% int8 MFMA peak)",
-        "value": F / (ms * 1e-3),
+        "value": F_total / (ms * 1e-3),
         "unit": "decoded frames/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -187,25 +239,25 @@ def main():
         "vs_baseline": None,
         "dtype": "i8",
         "data": "synthetic (seeded BPSK/AWGN frames, random payloads)",
-        "config": {"workload": "RM(3,7) N=128 K=64 (58+CRC-6), Eb/N0 %.2f dB, %d frames, int8 LLRs, "
-                               "SCL L=%d, T=%d, %d moves" % (args.ebn0, F, L, T, code.P),
-                   "frames": F, "stage2_frames": f2, "p_act": f2 / F,
-                   "paths_searched_per_iteration": cols.tolist(), "fer": fer},
-        "stage2_move_evals_per_s": moves_evals / (launches.sum() * 1e-3),
+        "config": {"workload": "; ".join(names) + "; int8 LLRs, SCL L=%d, T=%d" % (L, T),
+                   "frames": F_total, "stage2_frames": int(stats[0]), "p_act": int(stats[0]) / F_total,
+                   "paths_searched_per_iteration": stats[1:1 + T].tolist(), "fer": fer},
+        "stage2_move_evals_per_s": move_evals / (launches.sum() * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_INT8_DENSE_TOPS, "unit": "TOP/s",
-                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(),
+                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(args.workload),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 KiB)",
-                     "kernel": "search_i8_kernel",
+                     "kernel": "search_i8_kernel" if nseg == 1 else "search_i8_multi_kernel",
                      "launch_ms": launches.tolist(),
                      "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)"},
         "wall_s": wall,
         "ms_per_step_eager": ms_eager,
-        "search_tiles": {"variant": variant, "blocks_per_cu": bpc,
-                         **_lib_variants()[variant]},
+        "search_tiles": {"variant": variant, "blocks_per_cu": bpc, **_lib.mpwsd_search_variants()[variant]},
     }
+    if args.cpu_frames < 0:
+        args.cpu_frames = 4096 if args.workload == "rm38" else F_total
     if args.cpu_frames > 0:
         thr = args.cpu_threads or min(16, os.cpu_count() or 1)
-        res["cpu_baseline"] = cpu_baseline(wl, y, L, T, min(args.cpu_frames, F), thr)
+        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr)
     print(json.dumps(res))
 
 

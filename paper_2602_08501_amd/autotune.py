@@ -19,10 +19,10 @@ from . import _lib
 CACHE = os.environ.get("MPWSD_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "mpwsd", "tune.json"))
 
 
-def _key(stage2, code, F) -> str:
+def _key(stage2) -> str:
     name = torch.cuda.get_device_name(torch.device(stage2.device))
-    return "%s|RM(%d,%d)|L%d|T%d|F%d|%s" % (name, code.r, code.m, stage2.L, stage2.T, F,
-                                           "i8" if stage2.dt == _lib.MPWSD_I8 else "f32")
+    segs = "+".join("RM(%d,%d)xF%d" % (code.r, code.m, F) for code, F in stage2.codes_F)
+    return "%s|%s|L%d|T%d|%s" % (name, segs, stage2.L, stage2.T, "i8" if stage2.dt == _lib.MPWSD_I8 else "f32")
 
 
 def _load() -> dict:
@@ -44,8 +44,12 @@ def _save(d: dict) -> None:
         pass
 
 
-def candidates(N: int):
+def candidates(N: int, multi: bool = False):
+    """(variant, workgroups per CU) pairs to time; a batch of several codes
+    is searched by one launch that exists for the first three variants."""
     vs = _lib.mpwsd_search_variants()
+    if multi:
+        vs = vs[:3]
     kp = max(N, 64)
     lds_fit = (160 * 1024) // (2 * 128 * (kp + 16))
     out = []
@@ -58,35 +62,36 @@ def candidates(N: int):
 
 def tune(stage2, llrs, anchors, crc_oks, reps: int = 3, stream=None, use_cache: bool = True, verbose=False):
     """Returns (variant, blocks_per_cu) for this Stage2 and its inputs."""
-    code, F = stage2.codes_F[0]
-    key = _key(stage2, code, F)
+    key = _key(stage2)
     cache = _load() if use_cache else {}
     if key in cache:
         return tuple(cache[key]["choice"])
     stream = stream or torch.cuda.current_stream()
     T = stage2.T
     nseg = len(stage2.codes_F)
+    multi = nseg > 1 and stage2.dt == _lib.MPWSD_I8
+    n_launch = T if multi else T * nseg
     events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T * nseg)]
     for e in events:
         e.record(stream)
     ref = None
     results = []
-    for var, bpc in candidates(code.N):
+    for var, bpc in candidates(max(c.N for c, _ in stage2.codes_F), multi):
         times = []
         for r in range(reps + 1):
             stage2.run(llrs, anchors, crc_oks, stream=stream, events=events, variant=var, blocks_per_cu=bpc)
             stream.synchronize()
             if r == 0:
-                out = {k: v.clone() for k, v in stage2.outs[0].items()}
+                out = [{k: v.clone() for k, v in o.items()} for o in stage2.outs]
                 if ref is None:
                     ref = out
                 else:
-                    for k in ref:
-                        if not torch.equal(ref[k], out[k]):
+                    for k in ref[0]:
+                        if not all(torch.equal(a[k], b[k]) for a, b in zip(ref, out)):
                             raise RuntimeError("search variant %d / %d differs from variant %d in %s"
                                                % (var, bpc, results[0][1], k))
                 continue
-            times.append(sum(events[2 * t].elapsed_time(events[2 * t + 1]) for t in range(T * nseg)))
+            times.append(sum(events[2 * t].elapsed_time(events[2 * t + 1]) for t in range(n_launch)))
         results.append((min(times), var, bpc))
         if verbose:
             print("variant %d blocks/CU %d: %.3f ms" % (var, bpc, min(times)))
