@@ -118,7 +118,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2602_08501_amd import _lib, autotune
+    from paper_2602_08501_amd import _lib, autotune, complexity
     from paper_2602_08501_amd import decoder as D
     from paper_2602_08501_amd import synth
 
@@ -206,15 +206,19 @@ def main():
         ms_eager = e_start.elapsed_time(e_end) / args.steps
 
     # searched paths per iteration and segment (deterministic per segment)
-    per_seg_cols = []
+    per_seg_stats = []
     for i, (wl, F) in enumerate(segs if nseg > 1 else []):
         one = D.Stage2([(codes[i], F)], L, T, "i8", dev, want_moves=False)
         one.run([q_d[i]], [s1[i]["anchors"]], [s1[i]["crc_ok"]])
         torch.cuda.synchronize()
-        per_seg_cols.append(one.stats.cpu().numpy()[1:1 + T].astype(np.int64))
+        per_seg_stats.append(one.stats.cpu().numpy().astype(np.int64))
     stats = st.stats.cpu().numpy()
     if nseg == 1:
-        per_seg_cols = [stats[1:1 + T].astype(np.int64)]
+        per_seg_stats = [stats.astype(np.int64)]
+    per_seg_cols = [x[1:1 + T] for x in per_seg_stats]
+    ed_units = [complexity.report(c.N, c.K, c.P, c.w, L, T, F, int(x[0]), x[1:1 + T].tolist(),
+                                  ms if nseg == 1 else None)
+                for c, (_, F), x in zip(codes, segs, per_seg_stats)]
     dense_ops = sum(2.0 * c.P * c.N * cols for c, cols in zip(codes, per_seg_cols))  # per launch
     launches = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
                          for k in range(args.steps)]).mean(0)
@@ -249,6 +253,7 @@ def main():
                      "kernel": "search_i8_kernel" if nseg == 1 else "search_i8_multi_kernel",
                      "launch_ms": launches.tolist(),
                      "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)"},
+        "complexity_ed_units": ed_units if nseg > 1 else ed_units[0],
         "wall_s": wall,
         "ms_per_step_eager": ms_eager,
         "search_tiles": {"variant": variant, "blocks_per_cu": bpc, **_lib.mpwsd_search_variants()[variant]},
