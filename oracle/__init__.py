@@ -54,6 +54,9 @@ def _L():
         lib.orc_moves.argtypes = [i32, i32, P, i64, P]
         lib.orc_moves.restype = i64
         lib.orc_pack_supports.argtypes = [i32, i64, i32, P, P]
+        lib.orc_weight_distribution.argtypes = [i32, i32, P]
+        lib.orc_sphere.argtypes = [i32, i32, i32, P, i64, P]
+        lib.orc_sphere.restype = i64
         lib.orc_crc.argtypes = [P, i32, i32, u32, P]
         lib.orc_crc_ok.argtypes = [P, i32, i32, u32]
         lib.orc_quantize.argtypes = [P, i64, f32, P]
@@ -127,6 +130,37 @@ def moves(r: int, m: int):
         assert P2 == P
         _moves_cache[key] = (supp, w.value)
     return _moves_cache[key]
+
+
+SUPP_END = 0xFFFF  # pads support rows of moves lighter than the row stride
+
+
+def weight_distribution(r: int, m: int) -> np.ndarray:
+    """A[0..N]: codewords of RM(r, m) per weight, by visiting all 2^K (K <= 30)."""
+    A = np.zeros((1 << m) + 1, np.int64)
+    if _L().orc_weight_distribution(r, m, _p(A)) != 0:
+        raise ValueError("bad RM parameters or K too large")
+    return A
+
+
+_sphere_cache: dict = {}
+
+
+def sphere(r: int, m: int, radius: int):
+    """(supp[P][stride] uint16, stride): the nonzero words of S_radius(0) by
+    weight, then canonical order; rows padded with SUPP_END.  radius 1 gives
+    the table of ``moves`` (via a different enumeration)."""
+    key = (r, m, radius)
+    if key not in _sphere_cache:
+        st = ctypes.c_int()
+        P = _L().orc_sphere(r, m, radius, None, 0, ctypes.byref(st))
+        if P < 0:
+            raise ValueError("bad RM parameters, K too large, or too few weights")
+        supp = np.zeros((P, st.value), np.uint16)
+        P2 = _L().orc_sphere(r, m, radius, _p(supp), P, ctypes.byref(st))
+        assert P2 == P
+        _sphere_cache[key] = (supp, st.value)
+    return _sphere_cache[key]
 
 
 def pack_supports(m: int, supp: np.ndarray) -> np.ndarray:
@@ -220,16 +254,17 @@ def ml(r: int, m: int, mode: int, y):
 
 # ---------------------------------------------------------------- two-stage decoder
 def decode_batch(r: int, m: int, crc_len: int, crc_poly: int, L: int, T: int, mode: int,
-                 llr, threads: int = 1, frames=None):
+                 llr, threads: int = 1, frames=None, radius: int = 1):
     """Decode llr[F][N] (Sec. III).  Returns a dict of per-frame outputs.
 
     ``frames`` optionally restricts the work to a sub-range (f0, f1); the
-    outputs still have F rows (untouched rows are zero / -1).
+    outputs still have F rows (untouched rows are zero / -1).  ``radius``
+    selects the sphere S_radius(0) searched by stage 2.
     """
     llr = np.ascontiguousarray(llr, np.float64)
     F, n = llr.shape
     assert n == 1 << m
-    supp, w = moves(r, m)
+    supp, w = moves(r, m) if radius == 1 else sphere(r, m, radius)
     P = supp.shape[0]
     out = {
         "c": np.zeros((F, n), np.uint8),

@@ -31,6 +31,10 @@
 
 enum { ORC_INT = 0, ORC_F32 = 1, ORC_F64 = 2 };
 
+/* Move tables are support lists supp[P][stride] (ascending positions); a
+ * move of weight below the stride ends with this marker.                    */
+#define ORC_SUPP_END 0xFFFF
+
 static double rnd(int mode, double x) { return mode == ORC_F32 ? (double)(float)x : x; }
 
 static int popcount_int(unsigned v) { int c = 0; while (v) { c += v & 1u; v >>= 1; } return c; }
@@ -194,16 +198,119 @@ int64_t orc_moves(int r, int m, uint16_t* supp, int64_t cap, int* w_out)
 }
 
 /* Bit-packed rows: bit j of a row is byte j/8, bit j%8 (least significant
- * bit first).  rows[P][N/8]. */
+ * bit first).  rows[P][N/8].  Support rows may end early with 0xFFFF.      */
 void orc_pack_supports(int m, int64_t P, int w, const uint16_t* supp, uint8_t* rows)
 {
     int nb = (1 << m) / 8;
     memset(rows, 0, (size_t)(P * nb));
     for (int64_t p = 0; p < P; ++p)
-        for (int i = 0; i < w; ++i) {
+        for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) {
             int j = supp[p * w + i];
             rows[p * nb + j / 8] |= (uint8_t)(1u << (j % 8));
         }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Spheres of larger radius, Eq. (1)-(2): S_rho(0) is the union of the shells
+ * C_{d_l}(0), l = 0..rho, where d_0 = 0 < d_1 < d_2 < ... are the distinct
+ * weights that occur in the code.  The oracle finds them by visiting every
+ * codeword: the 2^K messages in Gray-code order, each step adding one row of
+ * G = F^{(x)m} (the row of the information position whose message bit
+ * changes), and the weight recounted in full.  K <= 30.                     */
+
+typedef void (*cw_visit)(const uint8_t* c, int n, int w, void* ctx);
+
+static int visit_codewords(int r, int m, cw_visit visit, void* ctx)
+{
+    int n, K;
+    if (orc_rm_dims(r, m, &n, &K) != 0 || K > 30) return -1;
+    int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    orc_rm_info_set(r, m, A);
+    uint8_t* c = (uint8_t*)calloc((size_t)n, 1);
+    visit(c, n, 0, ctx);
+    for (int64_t g = 1; g < ((int64_t)1 << K); ++g) {
+        /* Gray codes of g-1 and g differ in the lowest set bit of g */
+        int b = 0;
+        while (!((g >> b) & 1)) ++b;
+        int row = A[b];
+        for (int j = 0; j < n; ++j)
+            if ((j & ~row) == 0) c[j] ^= 1;
+        int w = 0;
+        for (int j = 0; j < n; ++j) w += c[j];
+        visit(c, n, w, ctx);
+    }
+    free(A);
+    free(c);
+    return 0;
+}
+
+static void count_weight(const uint8_t* c, int n, int w, void* ctx)
+{
+    (void)c; (void)n;
+    ((int64_t*)ctx)[w]++;
+}
+
+/* A[0..N]: the number of codewords of each weight.  Returns 0, or -1. */
+int orc_weight_distribution(int r, int m, int64_t* A)
+{
+    if (m < 1 || m > 10 || r < 0 || r > m) return -1;
+    memset(A, 0, sizeof(int64_t) * (size_t)((1 << m) + 1));
+    return visit_codewords(r, m, count_weight, A);
+}
+
+typedef struct { int wlo, whi, stride; int64_t count, cap; uint16_t* supp; } sphere_sink;
+
+static void collect_word(const uint8_t* c, int n, int w, void* ctx)
+{
+    sphere_sink* s = (sphere_sink*)ctx;
+    if (w < s->wlo || w > s->whi) return;
+    if (s->supp && s->count < s->cap) {
+        uint16_t* row = s->supp + s->count * s->stride;
+        int k = 0;
+        for (int j = 0; j < n; ++j) if (c[j]) row[k++] = (uint16_t)j;
+        while (k < s->stride) row[k++] = ORC_SUPP_END;
+    }
+    s->count++;
+}
+
+static int cmp_weight_supp(const void* a, const void* b)
+{
+    const uint16_t* x = (const uint16_t*)a;
+    const uint16_t* y = (const uint16_t*)b;
+    int wx = 0, wy = 0;
+    while (wx < g_cmp_w && x[wx] != ORC_SUPP_END) ++wx;
+    while (wy < g_cmp_w && y[wy] != ORC_SUPP_END) ++wy;
+    if (wx != wy) return wx < wy ? -1 : 1;
+    return cmp_supp(a, b);
+}
+
+/* The nonzero codewords of S_rho(0) (weights d_1 .. d_rho): supp[P][stride]
+ * receives the ascending support of each, padded with ORC_SUPP_END, sorted by
+ * weight and then by the support tuple compared lexicographically (for
+ * rho = 1 the order of orc_moves).  *stride = d_rho.  Fills supp when it is
+ * non-NULL and cap >= P.  Returns P, or -1 on bad arguments, short cap, or
+ * when the code has fewer than rho nonzero weights.                          */
+int64_t orc_sphere(int r, int m, int rho, uint16_t* supp, int64_t cap, int* stride)
+{
+    int n = 1 << m;
+    if (rho < 1) return -1;
+    int64_t* A = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    if (orc_weight_distribution(r, m, A) != 0) { free(A); return -1; }
+    int got = 0, wlo = -1, whi = -1;
+    for (int w = 1; w <= n && got < rho; ++w)
+        if (A[w]) { if (wlo < 0) wlo = w; whi = w; ++got; }
+    int64_t P = 0;
+    for (int w = wlo; w <= whi && got == rho; ++w) P += A[w];
+    free(A);
+    if (got < rho) return -1;
+    *stride = whi;
+    if (!supp) return P;
+    if (cap < P) return -1;
+    sphere_sink s = { wlo, whi, whi, 0, cap, supp };
+    visit_codewords(r, m, collect_word, &s);
+    g_cmp_w = whi;
+    qsort(supp, (size_t)s.count, sizeof(uint16_t) * (size_t)whi, cmp_weight_supp);
+    return s.count;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -387,7 +494,8 @@ double orc_metric(int mode, int n, const double* y, const uint8_t* c)
 /* Stage 2, Sec. III-B, Eq. (4), Alg. 1, with the correlation gain of Eq. (5).
  * For the path centred at c, moving to c xor w changes the squared distance
  * by 4 * sum_{j in supp(w)} z_j with z_j = y_j (1 - 2 c_j) = y_j x_j(c),
- * i.e. by -2 G(w).  Each iteration scores every move w_p of S_1(0) by
+ * i.e. by -2 G(w).  Each iteration scores every move w_p of the table (the
+ * nonzero words of S_rho(0), any radius; supp rows of stride w) by
  *     S_p = sum_{j in supp(w_p)} z_j        (ascending j, rnd after each add)
  * and takes p* = the smallest p attaining the minimum.  The move is accepted
  * iff S_p* < 0 (strict improvement, Sec. III-B); otherwise the path stops
@@ -406,11 +514,11 @@ void orc_stage2_path(int mode, int n, int64_t P, int w, const uint16_t* supp,
         double bs = 0.0;
         for (int64_t p = 0; p < P; ++p) {
             double s = 0.0;
-            for (int i = 0; i < w; ++i) s = rnd(mode, s + z[supp[p * w + i]]);
+            for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) s = rnd(mode, s + z[supp[p * w + i]]);
             if (best < 0 || s < bs) { best = p; bs = s; }
         }
         if (best >= 0 && bs < 0) {
-            for (int i = 0; i < w; ++i) c[supp[best * w + i]] ^= 1;
+            for (int i = 0; i < w && supp[best * w + i] != ORC_SUPP_END; ++i) c[supp[best * w + i]] ^= 1;
             log[t] = (int32_t)best;
         } else {
             log[t] = -1;
@@ -475,7 +583,7 @@ int orc_stage2_alg1(int n, int64_t P, int w, const uint16_t* supp, const double*
             uint8_t* c = paths_out + (size_t)k * n;
             for (int64_t p = 0; p < P; ++p) {
                 double g = 0.0;
-                for (int i = 0; i < w; ++i) {
+                for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) {
                     int j = supp[p * w + i];
                     double x = c[j] ? -1.0 : 1.0;
                     g += -2.0 * y[j] * x;
@@ -489,12 +597,12 @@ int orc_stage2_alg1(int n, int64_t P, int w, const uint16_t* supp, const double*
             for (int64_t t = 0; t < mm; ++t) {
                 int64_t p = gi[t].p;
                 memcpy(cand, c, (size_t)n);
-                for (int i = 0; i < w; ++i) cand[supp[p * w + i]] ^= 1;
+                for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) cand[supp[p * w + i]] ^= 1;
                 double d = orc_metric(ORC_F64, n, y, cand);
                 if (best < 0 || d < bestd || (d == bestd && p < best)) { best = p; bestd = d; }
             }
             if (best >= 0 && bestd < cur) {
-                for (int i = 0; i < w; ++i) c[supp[best * w + i]] ^= 1;
+                for (int i = 0; i < w && supp[best * w + i] != ORC_SUPP_END; ++i) c[supp[best * w + i]] ^= 1;
                 logs[k * J + it] = (int32_t)best;
                 updated = 1;
             } else {
