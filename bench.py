@@ -9,9 +9,11 @@ Default workload (the metric's): RM(3,7) (N=128, K=64 = 58 payload + CRC-6),
 BPSK over AWGN at Eb/N0 = 2.5 dB, 65536 frames, int8 LLRs (scale 8/sigma^2),
 L = 8 anchors, T = 8 iterations, 94488 moves (seeded synthetic data).
 Other workloads: --workload rm38 (RM(3,8), 32768 frames at 2.0 dB, L=16,
-T=12, 777240 moves) and --workload mixed (262144 frames, RM(2,6) / RM(2,7)
+T=12, 777240 moves), --workload mixed (262144 frames, RM(2,6) / RM(2,7)
 / RM(3,7) in equal shares at 2.5 dB, L=8, T=8, all codes' failing frames in
-one search launch per iteration).
+one search launch per iteration), --workload rm26 (65536 RM(2,6) frames at
+3.0 dB, L=8, T=8, 2604 moves) and --workload rm26s2 (the same frames with the
+sphere of radius 2: 2604 + 291648 moves).
 
 Prints one JSON line.  The roofline entry is for the stage-2 move-search
 kernel: dense int8 MFMA work 2 P N per searched path and iteration, over
@@ -41,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed"])
+    ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed", "rm26", "rm26s2"])
     ap.add_argument("--frames", type=int, default=0, help="override the workload's frame count")
     ap.add_argument("--ebn0", type=float, default=None, help="override the workload's Eb/N0")
     ap.add_argument("--seed", type=int, default=0)
@@ -55,11 +57,13 @@ def parse():
 
 
 def workload(args, synth):
-    """[(Workload, frames)], L, T."""
+    """[(Workload, frames)], L, T, sphere radius of the move tables."""
     if args.workload == "rm37":
         segs, L, T = [(synth.RM37, 65536)], 8, 8
     elif args.workload == "rm38":
         segs, L, T = [(synth.RM38, 32768)], 16, 12
+    elif args.workload in ("rm26", "rm26s2"):
+        segs, L, T = [(synth.RM26, 65536)], 8, 8
     else:
         segs = [(dataclasses.replace(w, ebn0_db=2.5), f)
                 for w, f in ((synth.RM26, 87382), (synth.RM27, 87381), (synth.RM37, 87381))]
@@ -68,7 +72,8 @@ def workload(args, synth):
         segs = [(dataclasses.replace(w, ebn0_db=args.ebn0), f) for w, f in segs]
     if args.frames:
         segs = [(w, max(1, args.frames // len(segs))) for w, f in segs]
-    return segs, L, T
+    radius = 2 if args.workload == "rm26s2" else 1
+    return segs, L, T, radius
 
 
 def recorded_traffic(workload_name):
@@ -90,7 +95,7 @@ def recorded_traffic(workload_name):
     return int(m.group(3))
 
 
-def cpu_baseline(segs, ys, L, T, nframes, threads):
+def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1):
     """The oracle on the first frames of every code's batch (the sample split
     evenly over the codes), int8 arithmetic, whole two-stage decode."""
     import oracle
@@ -98,11 +103,12 @@ def cpu_baseline(segs, ys, L, T, nframes, threads):
     for (wl, F), y in zip(segs, ys):
         n = min(max(1, nframes // len(segs)), len(y))
         qs.append(oracle.quantize(y[:n], wl.llr_scale).astype(np.float64))
-        oracle.moves(wl.r, wl.m)  # table built outside the timed region
+        oracle.moves(wl.r, wl.m) if radius == 1 else oracle.sphere(wl.r, wl.m, radius)  # built outside the timing
         parts.append("%d RM(%d,%d)" % (n, wl.r, wl.m))
     t0 = time.perf_counter()
     for (wl, F), q in zip(segs, qs):
-        oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads)
+        oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads,
+                            radius=radius)
     dt = time.perf_counter() - t0
     n = sum(len(q) for q in qs)
     return {"value": n / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
@@ -122,7 +128,7 @@ def main():
     from paper_2602_08501_amd import decoder as D
     from paper_2602_08501_amd import synth
 
-    segs, L, T = workload(args, synth)
+    segs, L, T, radius = workload(args, synth)
     dev = "cuda:0"
     stream = torch.cuda.Stream()
     if args.calib_copy > 0:
@@ -135,7 +141,7 @@ def main():
     codes, ys, txs, y_d, q_d, s1 = [], [], [], [], [], []
     for wl, F in segs:
         pay, c_tx, y = synth.generate(wl, args.seed, 0, F)
-        code = D.Code(wl.r, wl.m, dev)
+        code = D.Code(wl.r, wl.m, dev, radius=radius)
         codes.append(code)
         ys.append(y)
         txs.append(c_tx)
@@ -228,7 +234,8 @@ def main():
         cw = np.unpackbits(st.outs[i]["cw"].cpu().numpy(), axis=-1, bitorder="little")
         fer.append(float((cw != txs[i]).any(1).mean()))
     move_evals = float(sum(c.P * cols.sum() for c, cols in zip(codes, per_seg_cols)))
-    names = ["RM(%d,%d) N=%d P=%d Eb/N0 %.2f dB %d frames" % (w.r, w.m, c.N, c.P, w.ebn0_db, F)
+    names = ["RM(%d,%d) N=%d P=%d%s Eb/N0 %.2f dB %d frames"
+             % (w.r, w.m, c.N, c.P, " (sphere S_%d)" % radius if radius > 1 else "", w.ebn0_db, F)
              for (w, F), c in zip(segs, codes)]
     res = {
         "metric": "decoded frames/sec at FER parity; stage-2 move-evals/sec (% int8 MFMA peak)",
@@ -259,10 +266,10 @@ def main():
         "search_tiles": {"variant": variant, "blocks_per_cu": bpc, **_lib.mpwsd_search_variants()[variant]},
     }
     if args.cpu_frames < 0:
-        args.cpu_frames = 4096 if args.workload == "rm38" else F_total
+        args.cpu_frames = {"rm38": 4096, "rm26s2": 8192}.get(args.workload, F_total)
     if args.cpu_frames > 0:
         thr = args.cpu_threads or min(16, os.cpu_count() or 1)
-        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr)
+        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr, radius)
     print(json.dumps(res))
 
 

@@ -78,6 +78,28 @@ int mpwsd_build_moves(int r, int m, uint8_t* moves, size_t cap_bytes,
                       int64_t* P, int* N, int* w);
 
 /*
+ * mpwsd_build_sphere - the code-weight sphere S_radius(0) without the zero
+ * word (Sec. II-C, Eq. (1)-(2)): every nonzero codeword of RM(r, m) whose
+ * weight is one of the `radius` smallest nonzero weights of the code (the
+ * shells d_1 .. d_radius).  radius = 1 is mpwsd_build_moves.  For radius >= 2
+ * the code must have dimension K <= 30 (the shells are found by visiting all
+ * 2^K codewords on the host's threads; RM(2,7), K = 29, takes about a second).
+ *
+ * Rows are sorted by weight, then canonically as in mpwsd_build_moves, so the
+ * first rows are the table of radius 1.  The stage-2 search treats every row
+ * the same way whatever its weight (Eq. (5) holds for any move).
+ *
+ * moves: HOST buffer of cap_bytes bytes receiving P rows of N/8 bytes, or
+ *        NULL to query the sizes only.
+ * P, N, w_max (the largest weight in the table): out (any may be NULL).
+ * Errors: MPWSD_ERR_UNSUPPORTED for r, m out of range or K > 30 with
+ * radius >= 2; MPWSD_ERR_ARG when the code has fewer than `radius` nonzero
+ * weights; MPWSD_ERR_SIZE as for mpwsd_build_moves.  Host-only, thread-safe.
+ */
+int mpwsd_build_sphere(int r, int m, int radius, uint8_t* moves, size_t cap_bytes,
+                       int64_t* P, int* N, int* w_max);
+
+/*
  * mpwsd_quantize_llr - int8 LLR quantizer (device):
  *   q[i] = clamp(round_half_even(fl32(y[i] * scale)), -127, 127)
  * with scale typically 8 / sigma^2 (four times the LLR 2y/sigma^2).
@@ -121,8 +143,10 @@ int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L,
  */
 typedef struct mpwsd_segment {
     int r, m;                  /* code RM(r, m) */
-    const uint8_t* moves;      /* device [P][N/8], the table of mpwsd_build_moves */
-    int64_t P;                 /* number of moves */
+    const uint8_t* moves;      /* device [P][N/8], the table of mpwsd_build_moves
+                                  or mpwsd_build_sphere */
+    int64_t P;                 /* number of moves: the size of one of those
+                                  tables for RM(r, m) (checked) */
     const void* llr;           /* device [F][N]: int8 q or float y */
     int dtype;                 /* MPWSD_I8 or MPWSD_F32 */
     int64_t F;                 /* frames */
@@ -255,7 +279,8 @@ typedef struct mpwsd_server mpwsd_server;
 
 typedef struct mpwsd_server_code {
     int r, m;                /* RM(r, m), 5 <= m <= 8 */
-    const uint8_t* moves;    /* device [P][N/8] move table (mpwsd_build_moves) */
+    const uint8_t* moves;    /* device [P][N/8] move table (mpwsd_build_moves or
+                                mpwsd_build_sphere) */
     int64_t P;
     int L, T;                /* list size (power of two <= 32), iterations */
     int crc_len;             /* CRC length (0: no CRC, every frame goes on) */
@@ -269,7 +294,7 @@ typedef struct mpwsd_result {
     int32_t stage;           /* 1: decided by stage 1, 2: by stage 2 */
     int32_t k;               /* chosen path (0 for stage 1) */
     int32_t metric;          /* M(c) = sum_{c_j=1} q_j of the decision */
-    uint8_t cw[32];          /* decision, N/8 bytes used */
+    uint8_t cw[32];          /* decision in the first N/8 bytes, the rest 0 */
     double t_submit;         /* host seconds (steady clock) at submission */
     double t_done;           /* host seconds at which the host saw the result */
 } mpwsd_result;

@@ -70,6 +70,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_last_error.restype = ctypes.c_char_p
         lib.mpwsd_last_error.argtypes = []
         lib.mpwsd_build_moves.argtypes = [_i, _i, _p, _sz, _p, _p, _p]
+        lib.mpwsd_build_sphere.argtypes = [_i, _i, _i, _p, _sz, _p, _p, _p]
         lib.mpwsd_quantize_llr.argtypes = [_p, _i64, _f, _p, _p, _p]
         lib.mpwsd_stage1_scl.argtypes = [_i, _i, _i, _u32, _i, _p, _i, _i64, _p, _p, _p, _p]
         lib.mpwsd_workspace_bytes.argtypes = [ctypes.POINTER(Segment), _i, _i, _i]
@@ -90,7 +91,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_server_poll.argtypes = [_p, ctypes.POINTER(Result), _i]
         lib.mpwsd_server_destroy.argtypes = [_p]
         lib.mpwsd_serve_trace.argtypes = [_p, _i64, _p, _p, _p, _p, ctypes.POINTER(_p), ctypes.POINTER(Result)]
-        for name in ("mpwsd_build_moves", "mpwsd_quantize_llr", "mpwsd_stage1_scl", "mpwsd_decode_batch",
+        for name in ("mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_quantize_llr", "mpwsd_stage1_scl", "mpwsd_decode_batch",
                      "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
                      "mpwsd_graph_launch", "mpwsd_graph_destroy", "mpwsd_server_create", "mpwsd_server_submit",
                      "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"):
@@ -121,6 +122,14 @@ def mpwsd_build_moves(r: int, m: int, moves_ptr, cap_bytes: int):
     P, N, w = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
     rc = load().mpwsd_build_moves(r, m, moves_ptr, cap_bytes, ctypes.byref(P), ctypes.byref(N),
                                   ctypes.byref(w))
+    return rc, P.value, N.value, w.value
+
+
+def mpwsd_build_sphere(r: int, m: int, radius: int, moves_ptr, cap_bytes: int):
+    """Returns (rc, P, N, w_max); moves_ptr may be None for a size query."""
+    P, N, w = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+    rc = load().mpwsd_build_sphere(r, m, radius, moves_ptr, cap_bytes, ctypes.byref(P), ctypes.byref(N),
+                                   ctypes.byref(w))
     return rc, P.value, N.value, w.value
 
 

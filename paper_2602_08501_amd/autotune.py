@@ -21,7 +21,7 @@ CACHE = os.environ.get("MPWSD_TUNE_CACHE", os.path.join(os.path.expanduser("~"),
 
 def _key(stage2) -> str:
     name = torch.cuda.get_device_name(torch.device(stage2.device))
-    segs = "+".join("RM(%d,%d)xF%d" % (code.r, code.m, F) for code, F in stage2.codes_F)
+    segs = "+".join("RM(%d,%d)P%dxF%d" % (code.r, code.m, code.P, F) for code, F in stage2.codes_F)
     return "%s|%s|L%d|T%d|%s" % (name, segs, stage2.L, stage2.T, "i8" if stage2.dt == _lib.MPWSD_I8 else "f32")
 
 

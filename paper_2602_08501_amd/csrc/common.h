@@ -20,6 +20,14 @@ int rm_dimension(int r, int m);
 // Number of minimum-weight codewords of RM(r, m) (flats of dimension m - r).
 int64_t rm_min_weight_count(int r, int m);
 
+// Largest move table the kernels index (move indices are 32-bit in the
+// search keys, with room for a 128-row tail chunk).
+constexpr int64_t kMaxMoves = (int64_t(1) << 31) - 256;
+
+// True when P is the size of a move table the library builds for RM(r, m):
+// the minimum-weight words, or (K <= 30) the nonzero words of some S_rho(0).
+bool valid_move_count(int r, int m, int64_t P);
+
 // Compute units of the current device (cached per device).
 int device_cu_count();
 

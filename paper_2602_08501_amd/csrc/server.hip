@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
             r.stage = 1;
             r.k = 0;
             r.metric = m;
-            for (int b = 0; b < NB; ++b) r.cw[b] = a[b];
+            for (int b = 0; b < 32; ++b) r.cw[b] = b < NB ? a[b] : 0;
         }
         // the paths of the other new frames become active columns
         const bool join = live && !decided;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void srv_resolve_kernel(
             r.k = kb;
             r.metric = mb;
             const uint8_t* c = cw + ((size_t)slot * L + kb) * NB;
-            for (int b = 0; b < NB; ++b) r.cw[b] = c[b];
+            for (int b = 0; b < 32; ++b) r.cw[b] = b < NB ? c[b] : 0;
         }
     }
 }
@@ -289,8 +289,9 @@ int check_codes(const mpwsd_server_code* codes, int ncodes)
         const auto& c = codes[i];
         if (c.m < 5 || c.m > 8 || c.r < 1 || c.r >= c.m)
             return fail(MPWSD_ERR_UNSUPPORTED, "server code %d: need 1 <= r < m, 5 <= m <= 8", i);
-        if (c.P != mpwsd::rm_min_weight_count(c.r, c.m))
-            return fail(MPWSD_ERR_ARG, "server code %d: P is not the move count of RM(%d,%d)", i, c.r, c.m);
+        if (c.P > mpwsd::kMaxMoves || !mpwsd::valid_move_count(c.r, c.m, c.P))
+            return fail(MPWSD_ERR_ARG, "server code %d: P=%lld is not the size of a move table of RM(%d,%d)", i,
+                        (long long)c.P, c.r, c.m);
         if (c.L < 1 || c.L > 32 || (c.L & (c.L - 1)) || c.T < 1 || c.T > 64)
             return fail(MPWSD_ERR_UNSUPPORTED, "server code %d: L must be a power of two <= 32, 1 <= T <= 64", i);
         if (c.capacity < 1 || (int64_t)c.capacity * c.L > (1 << 26))

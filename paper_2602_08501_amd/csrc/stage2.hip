@@ -549,10 +549,11 @@ __device__ inline uint32_t orderable(float v)
 }
 
 // One wave per workgroup: 64 columns, z held in LDS as [position][column]
-// (N <= 256 floats per column), supports of 64 moves staged per step.
+// (N <= 256 floats per column), supports and weights of 64 moves staged per
+// step (moves of any weight: tables of larger spheres mix weights).
 template <int N>
 __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restrict__ z, const uint8_t* __restrict__ moves,
-                                                          int w, int64_t P, const int32_t* __restrict__ act,
+                                                          int64_t P, const int32_t* __restrict__ act,
                                                           const int32_t* __restrict__ hdr, int t,
                                                           unsigned long long* __restrict__ keys)
 {
@@ -560,7 +561,8 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
     constexpr int MC = 64;    // moves per staged step
     constexpr int NB = N / 8;
     __shared__ float zs[N * CT];
-    __shared__ uint8_t sup[MC * (N / 2)];  // supports (w <= N / 2)
+    __shared__ uint8_t sup[MC * N];  // ascending supports
+    __shared__ int wts[MC];           // their weights
     const int n = hdr[2 + t];
     if (n <= 0) return;
     const int lane = threadIdx.x;
@@ -589,18 +591,20 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
                     for (int wd = 0; wd < N / 32; ++wd) {
                         uint32_t bits = *(const uint32_t*)(row + 4 * wd);
                         while (bits) {
-                            sup[lane * (N / 2) + cnt++] = (uint8_t)(32 * wd + __builtin_ctz(bits));
+                            sup[lane * N + cnt++] = (uint8_t)(32 * wd + __builtin_ctz(bits));
                             bits &= bits - 1;
                         }
                     }
+                    wts[lane] = cnt;
                 }
             }
             __syncthreads();
             const int pm = (int)std::min<int64_t>(MC, P - (int64_t)k * MC);
             for (int q = 0; q < pm; ++q) {
-                const uint8_t* sp = sup + q * (N / 2);
+                const uint8_t* sp = sup + q * N;
+                const int wq = wts[q];
                 float s = zs[sp[0] * CT + lane];
-                for (int i = 1; i < w; ++i) s = __fadd_rn(s, zs[sp[i] * CT + lane]);
+                for (int i = 1; i < wq; ++i) s = __fadd_rn(s, zs[sp[i] * CT + lane]);
                 const unsigned long long kk =
                     ((unsigned long long)orderable(s) << 32) | (unsigned long long)((int64_t)k * MC + q);
                 best = kk < best ? kk : best;
@@ -740,14 +744,13 @@ void launch_search_i8_n(const int8_t* zneg, const uint8_t* moves, int64_t P, con
 
 void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream_t s, int grid)
 {
-    const int wt = 1 << (sg.m - sg.r);
     const float* z = (const float*)w.z;
     unsigned long long* keys = (unsigned long long*)w.key64;
     switch (sg.m) {
-    case 5: hipLaunchKernelGGL(search_f32_kernel<32>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
-    case 6: hipLaunchKernelGGL(search_f32_kernel<64>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
-    case 7: hipLaunchKernelGGL(search_f32_kernel<128>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
-    default: hipLaunchKernelGGL(search_f32_kernel<256>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, wt, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    case 5: hipLaunchKernelGGL(search_f32_kernel<32>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    case 6: hipLaunchKernelGGL(search_f32_kernel<64>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    case 7: hipLaunchKernelGGL(search_f32_kernel<128>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
+    default: hipLaunchKernelGGL(search_f32_kernel<256>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
     }
 }
 
@@ -900,9 +903,10 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
         if (s.dtype != MPWSD_I8 && s.dtype != MPWSD_F32) return fail(MPWSD_ERR_ARG, "segment %d: bad dtype", i);
         if (s.dtype != segs[0].dtype) return fail(MPWSD_ERR_ARG, "segment %d: all segments need the same dtype", i);
         if (s.F < 0) return fail(MPWSD_ERR_ARG, "segment %d: F < 0", i);
-        if (s.P != mpwsd::rm_min_weight_count(s.r, s.m))
-            return fail(MPWSD_ERR_ARG, "segment %d: P=%lld is not the move count %lld of RM(%d,%d)", i,
-                        (long long)s.P, (long long)mpwsd::rm_min_weight_count(s.r, s.m), s.r, s.m);
+        if (s.P > mpwsd::kMaxMoves || !mpwsd::valid_move_count(s.r, s.m, s.P))
+            return fail(MPWSD_ERR_ARG,
+                        "segment %d: P=%lld is not the size of a move table of RM(%d,%d) (minimum-weight words: %lld)",
+                        i, (long long)s.P, s.r, s.m, (long long)mpwsd::rm_min_weight_count(s.r, s.m));
         if (s.F * (int64_t)L > INT_MAX / 2) return fail(MPWSD_ERR_UNSUPPORTED, "segment %d: F * L too large", i);
         if (check_ptrs && s.F > 0 && (!s.moves || !s.llr || !s.anchors || !s.out_cw))
             return fail(MPWSD_ERR_ARG, "segment %d: null pointer", i);

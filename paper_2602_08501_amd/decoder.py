@@ -11,12 +11,15 @@ from . import _lib
 from ._lib import MPWSD_F32, MPWSD_I8, Segment, check
 
 
-def build_moves_host(r: int, m: int) -> np.ndarray:
-    """Move table S_1(0) of RM(r, m), [P][N/8] uint8 (host, via the library)."""
-    rc, P, N, w = _lib.mpwsd_build_moves(r, m, None, 0)
+_POPCOUNT8 = np.array([bin(i).count("1") for i in range(256)], np.uint8)
+
+
+def build_moves_host(r: int, m: int, radius: int = 1) -> np.ndarray:
+    """Move table S_radius(0) \\ {0} of RM(r, m), [P][N/8] uint8 (host, via the library)."""
+    rc, P, N, w = _lib.mpwsd_build_sphere(r, m, radius, None, 0)
     check(rc)
     buf = np.zeros((P, N // 8), np.uint8)
-    rc, P, N, w = _lib.mpwsd_build_moves(r, m, buf.ctypes.data, buf.nbytes)
+    rc, P, N, w = _lib.mpwsd_build_sphere(r, m, radius, buf.ctypes.data, buf.nbytes)
     check(rc)
     return buf
 
@@ -31,13 +34,15 @@ def _stream(stream):
 
 
 class Code:
-    """Device-resident move table of RM(r, m)."""
+    """Device-resident move table of RM(r, m): the sphere S_radius(0)."""
 
-    def __init__(self, r: int, m: int, device="cuda:0"):
-        self.r, self.m, self.N = r, m, 1 << m
-        host = build_moves_host(r, m)
+    def __init__(self, r: int, m: int, device="cuda:0", radius: int = 1):
+        self.r, self.m, self.N, self.radius = r, m, 1 << m, radius
+        host = build_moves_host(r, m, radius)
         self.P = host.shape[0]
-        self.w = 1 << (m - r)
+        wts = _POPCOUNT8[host].sum(1, dtype=np.int64)
+        self.w_max = int(wts.max())
+        self.w = float(wts.mean())  # mean move weight (2^(m-r) for radius 1)
         self.moves = torch.from_numpy(host).to(device)
         self.K = sum(math.comb(m, d) for d in range(r + 1))
 

@@ -14,7 +14,7 @@ from paper_2602_08501_amd._lib import Segment
 def test_library_exports_every_declared_call():
     lib = _lib.load()
     names = _lib.header_functions()
-    assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_quantize_llr",
+    assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_quantize_llr",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
                           "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy",
@@ -56,6 +56,29 @@ def test_build_moves_errors():
     assert "need" in _lib.last_error()
 
 
+@pytest.mark.parametrize("r,m,radius", [(2, 6, 2), (2, 5, 2), (2, 5, 3), (1, 5, 2), (1, 6, 1), (2, 6, 1)])
+def test_sphere_table_matches_oracle(r, m, radius):
+    rc, P, N, wmax = _lib.mpwsd_build_sphere(r, m, radius, None, 0)
+    assert rc == 0, _lib.last_error()
+    supp, stride = oracle.sphere(r, m, radius)
+    assert (P, N, wmax) == (len(supp), 1 << m, stride)
+    buf = np.zeros((P, N // 8), np.uint8)
+    rc, *_ = _lib.mpwsd_build_sphere(r, m, radius, buf.ctypes.data, buf.nbytes)
+    assert rc == 0
+    assert np.array_equal(buf, oracle.pack_supports(m, supp))
+
+
+def test_build_sphere_errors():
+    rc, *_ = _lib.mpwsd_build_sphere(3, 7, 2, None, 0)      # K = 64: no exhaustive walk
+    assert rc == _lib.MPWSD_ERR_UNSUPPORTED and "K" in _lib.last_error()
+    rc, *_ = _lib.mpwsd_build_sphere(1, 4, 3, None, 0)      # RM(1,4): weights 8 and 16 only
+    assert rc == _lib.MPWSD_ERR_ARG
+    rc, *_ = _lib.mpwsd_build_sphere(2, 6, 0, None, 0)
+    assert rc == _lib.MPWSD_ERR_UNSUPPORTED
+    rc, P, *_ = _lib.mpwsd_build_sphere(2, 6, 2, np.zeros(8, np.uint8).ctypes.data, 8)
+    assert rc == _lib.MPWSD_ERR_SIZE and P == 294252
+
+
 def _seg(**kw):
     d = dict(r=3, m=7, moves=0x1000, P=94488, llr=0x2000, dtype=0, F=16, anchors=0x3000,
              crc_ok=None, out_cw=0x4000, out_k=None, out_metric=None, out_moves=None)
@@ -78,11 +101,15 @@ def test_decode_batch_validates_before_enqueue():
         ([_seg(F=-1)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(llr=None)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(moves=0x1001)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(r=2, m=6, P=2604 + 291647)], 8, 8, _lib.MPWSD_ERR_ARG),   # not a sphere size of RM(2,6)
     ]
     for segs, L, T, code in cases:
         if segs[-1].llr and segs[-1].moves % 4 == 0:  # size query ignores pointers
             assert _lib.mpwsd_workspace_bytes(segs, L, T) == 0
         assert _lib.mpwsd_decode_batch(segs, L, T, 0x10000, 1 << 40, None, None) == code, _lib.last_error()
+    # every sphere size of RM(2,6) is accepted: S_1, S_2 and S_3 without the zero word
+    for P in (2604, 2604 + 291648, 2604 + 291648 + 888832):
+        assert _lib.mpwsd_workspace_bytes([_seg(r=2, m=6, P=P)], 8, 8) > 0, _lib.last_error()
     # workspace too small / missing / misaligned
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10000, ok - 1, None, None) == _lib.MPWSD_ERR_SIZE
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, None, ok, None, None) == _lib.MPWSD_ERR_SIZE

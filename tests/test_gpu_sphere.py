@@ -1,0 +1,149 @@
+"""GPU parity for spheres of radius >= 2 (Eq. (1)-(2)): move tables that mix
+weights, built by mpwsd_build_sphere, searched by the same stage-2 kernels.
+
+Every case runs the whole two-stage decoder through the C-ABI and compares
+with the oracle's decoder on the oracle's own S_rho(0) table: decisions,
+chosen paths, metrics and every logged move index bit-exactly (int8 and the
+binary32 form), plus the per-iteration active counts.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_08501_amd import decoder as D
+from paper_2602_08501_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+_codes = {}
+
+
+def code(r, m, radius):
+    if (r, m, radius) not in _codes:
+        _codes[(r, m, radius)] = D.Code(r, m, DEV, radius=radius)
+    return _codes[(r, m, radius)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def unpack(t):
+    return np.unpackbits(t.cpu().numpy(), axis=-1, bitorder="little")
+
+
+# (name, workload, radius, L, T, frames)
+CASES = [
+    ("rm26_r2", dataclasses.replace(synth.RM26, ebn0_db=1.5), 2, 8, 4, 160),
+    ("rm25_r3", synth.Workload(r=2, m=5, k_pay=10, ebn0_db=1.0, wid=10), 3, 4, 4, 160),
+    ("rm15_r2_nocrc", synth.Workload(r=1, m=5, k_pay=6, crc_len=0, ebn0_db=0.0, wid=11), 2, 2, 3, 96),
+]
+
+
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_weight_n_move_all_ones(dtype):
+    """RM(1,5), radius 2: the table ends with the all-one word (weight N).
+    Anchor 0 of every frame is the complement of the sent codeword, so the
+    all-one move is the best first step; anchor 1 is a random codeword."""
+    say("case: all-one move", dtype)
+    wl = synth.Workload(r=1, m=5, k_pay=6, crc_len=0, ebn0_db=2.0, wid=12)
+    F, L, T = 64, 2, 3
+    pay, c, y = synth.generate(wl, 9, 0, F)
+    q = oracle.quantize(y, wl.llr_scale)
+    obs = q if dtype == "i8" else y
+    rng = np.random.default_rng(12)
+    G_rows = oracle.rm_info_set(1, 5)
+    anchors = np.zeros((F, L, 32), np.uint8)
+    for f in range(F):
+        anchors[f, 0] = c[f] ^ 1
+        u = np.zeros(32, np.uint8)
+        u[G_rows] = rng.integers(0, 2, len(G_rows))
+        anchors[f, 1] = oracle.encode(5, u)
+    cd = code(1, 5, 2)
+    supp, stride = oracle.sphere(1, 5, 2)
+    assert stride == 32 and cd.P == 63
+    anc = torch.from_numpy(np.packbits(anchors, axis=-1, bitorder="little")).to(DEV)
+    st = D.Stage2([(cd, F)], L, T, dtype, DEV)
+    out = st.run([torch.from_numpy(obs).to(DEV)], [anc], [None])[0]
+    torch.cuda.synchronize()
+    mode = oracle.INT if dtype == "i8" else oracle.F32
+    logs = out["moves"].cpu().numpy()
+    cw = unpack(out["cw"])
+    for f in range(F):
+        paths, rlogs, met, kb = oracle.stage2_frame(mode, supp, obs[f].astype(np.float64), anchors[f], T)
+        assert np.array_equal(logs[f], rlogs), f
+        assert np.array_equal(cw[f], paths[kb]), f
+    assert (logs[:, 0, 0] == 62).mean() > 0.9   # the all-one word is move 62
+
+
+@pytest.mark.parametrize("name,wl,radius,L,T,F", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_sphere_decode_parity(name, wl, radius, L, T, F, dtype):
+    say("case: sphere decode", name, dtype)
+    pay, c, y = synth.generate(wl, 7, 0, F)
+    q = oracle.quantize(y, wl.llr_scale)
+    obs = q if dtype == "i8" else y
+    cd = code(wl.r, wl.m, radius)
+    supp, stride = oracle.sphere(wl.r, wl.m, radius)
+    assert cd.P == len(supp) and cd.w_max == stride
+    assert np.array_equal(cd.moves.cpu().numpy(), oracle.pack_supports(wl.m, supp))
+    llr = torch.from_numpy(obs).to(DEV)
+    s1 = D.stage1(cd, L, llr, wl.crc_len, wl.crc_poly)
+    crc_ok = s1["crc_ok"] if wl.crc_len else None
+    st = D.Stage2([(cd, F)], L, T, dtype, DEV)
+    out = st.run([llr], [s1["anchors"]], [crc_ok])[0]
+    torch.cuda.synchronize()
+    stats = st.stats.cpu().numpy()
+    mode = oracle.INT if dtype == "i8" else oracle.F32
+    ref = oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, mode, obs.astype(np.float64),
+                              threads=8, radius=radius)
+    nfail = int((ref["crc_ok"] == 0).sum())
+    assert stats[0] == nfail and stats[1] == nfail * L
+    assert np.array_equal(out["moves"].cpu().numpy(), ref["logs"])
+    assert np.array_equal(unpack(out["cw"]), ref["c"])
+    assert np.array_equal(out["k"].cpu().numpy(), ref["k"])
+    met = out["metric"].cpu().numpy()
+    if dtype == "i8":
+        assert np.array_equal(met, ref["metric"].astype(np.int32))
+    else:
+        assert np.array_equal(met.view(np.float32), ref["metric"].astype(np.float32))
+    logs = ref["logs"][ref["crc_ok"] == 0]
+    for t in range(1, T):
+        assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
+    used = logs[logs >= 0]
+    outside = int((used >= oracle.moves(wl.r, wl.m)[0].shape[0]).sum())
+    say("  failing", nfail, "searched", stats[1:1 + T].tolist(), "moves outside shell 1:", outside)
+    if name != "rm15_r2_nocrc":
+        assert outside > 0   # the second shell is exercised
+
+
+def test_sphere_segment_beside_radius1_segment():
+    """One decode call, two segments: RM(2,6) with S_2 (294252 moves) and
+    RM(3,7) with S_1, both searched by the multi-code launch."""
+    say("case: sphere + shell-1 segments in one call")
+    wa = dataclasses.replace(synth.RM26, ebn0_db=1.5)
+    wb = dataclasses.replace(synth.RM37, ebn0_db=2.0)
+    L, T = 4, 4
+    segs, refs, llrs, s1s = [], [], [], []
+    for wl, radius, F in ((wa, 2, 96), (wb, 1, 128)):
+        pay, c, y = synth.generate(wl, 8, 0, F)
+        q = oracle.quantize(y, wl.llr_scale)
+        cd = code(wl.r, wl.m, radius)
+        llr = torch.from_numpy(q).to(DEV)
+        s1s.append(D.stage1(cd, L, llr, wl.crc_len, wl.crc_poly))
+        llrs.append(llr)
+        segs.append((cd, F))
+        refs.append(oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT,
+                                        q.astype(np.float64), threads=8, radius=radius))
+    st = D.Stage2(segs, L, T, "i8", DEV)
+    outs = st.run(llrs, [s["anchors"] for s in s1s], [s["crc_ok"] for s in s1s])
+    torch.cuda.synchronize()
+    for out, ref in zip(outs, refs):
+        assert np.array_equal(out["moves"].cpu().numpy(), ref["logs"])
+        assert np.array_equal(unpack(out["cw"]), ref["c"])
+        assert np.array_equal(out["metric"].cpu().numpy(), ref["metric"].astype(np.int32))

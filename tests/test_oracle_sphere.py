@@ -16,7 +16,6 @@ weight distribution and its S_rho(0) tables.
 * with the sphere taken as the whole code, one stage-2 step from any anchor
   lands on a maximum-likelihood codeword (brute force).
 """
-import itertools
 import math
 
 import numpy as np
