@@ -66,6 +66,7 @@ def _L():
         lib.orc_stage2_path.argtypes = [i32, i32, i64, i32, P, P, P, i32, P]
         lib.orc_stage2_frame.argtypes = [i32, i32, i64, i32, P, P, i32, P, i32, P, P, P]
         lib.orc_stage2_alg1.argtypes = [i32, i64, i32, P, P, i32, P, i32, i64, P, P]
+        lib.orc_osd.argtypes = [i32, i32, i32, i32, i32, P, P, P, P]
         lib.orc_ml.argtypes = [i32, i32, i32, P, P]
         lib.orc_ml.restype = ctypes.c_double
         lib.orc_decode_batch.argtypes = [i32, i32, i32, u32, i32, i32, i32, i64, i32, P,
@@ -245,6 +246,20 @@ def stage2_alg1(supp: np.ndarray, y, anchors, J: int, mfilt: int):
     return paths, logs, kb
 
 
+def osd(r: int, m: int, order: int, L: int, mode: int, llr):
+    """OSD(order) list of one frame: (anchors[n][N], metric[n], mrb[K]),
+    n = min(L, number of candidates), smallest metric first."""
+    llr = np.ascontiguousarray(llr, np.float64)
+    N, K = rm_dims(r, m)
+    anchors = np.zeros((L, N), np.uint8)
+    met = np.zeros(L, np.float64)
+    mrb = np.zeros(K, np.int32)
+    nl = _L().orc_osd(r, m, order, L, mode, _p(llr), _p(anchors), _p(met), _p(mrb))
+    if nl < 0:
+        raise ValueError("bad OSD parameters")
+    return anchors[:nl], met[:nl], mrb
+
+
 def ml(r: int, m: int, mode: int, y):
     y = np.ascontiguousarray(y, np.float64)
     c = np.zeros(1 << m, np.uint8)
@@ -288,4 +303,40 @@ def decode_batch(r: int, m: int, crc_len: int, crc_poly: int, L: int, T: int, mo
         # one frame per task keeps the threads busy when stage 2 is uneven
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(lambda f: run(f, f + 1), range(f0, f1)))
+    return out
+
+
+def decode_osd_batch(r: int, m: int, order: int, L: int, T: int, mode: int, llr, threads: int = 1,
+                     radius: int = 1):
+    """OSD(order) stage 1 and stage 2 on every frame (always-on mode, Sec.
+    III-C: no CRC, P_act = 1).  Returns anchors, metric of the anchors, the
+    decision, the chosen path, its metric and the move logs per frame."""
+    llr = np.ascontiguousarray(llr, np.float64)
+    F, n = llr.shape
+    supp, w = moves(r, m) if radius == 1 else sphere(r, m, radius)
+    out = {
+        "anchors": np.zeros((F, L, n), np.uint8),
+        "anchor_metric": np.zeros((F, L), np.float64),
+        "c": np.zeros((F, n), np.uint8),
+        "k": np.zeros(F, np.int32),
+        "metric": np.zeros(F, np.float64),
+        "logs": np.full((F, L, T), -1, np.int32),
+    }
+
+    def run(f):
+        a, met, _ = osd(r, m, order, L, mode, llr[f])
+        out["anchors"][f] = a
+        out["anchor_metric"][f] = met
+        paths, logs, pm, kb = stage2_frame(mode, supp, llr[f], a, T)
+        out["c"][f] = paths[kb]
+        out["k"][f] = kb
+        out["metric"][f] = pm[kb]
+        out["logs"][f] = logs
+
+    if threads <= 1:
+        for f in range(F):
+            run(f)
+    else:
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(run, range(F)))
     return out

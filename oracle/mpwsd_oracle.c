@@ -471,6 +471,119 @@ int orc_scl(int m, int L, int mode, const double* llr, const uint8_t* frozen,
 }
 
 /* ------------------------------------------------------------------------- */
+/* Ordered-statistics decoding of order k (the OSD stage 1 of Sec. III-A and
+ * Sec. IV-A, after Fossorier and Lin).  For one received word:
+ *   1. rank the positions by reliability |llr_j|, largest first, ties to the
+ *      smaller position;
+ *   2. walk the positions in that order and keep each one whose column of G
+ *      is independent of the columns already kept, until K are kept: the most
+ *      reliable basis b_0 .. b_{K-1} (MRB, in reliability order).  Gaussian
+ *      elimination on the rows of G along the way leaves rows g_0 .. g_{K-1}
+ *      with g_i(b_t) = [i == t]: the codeword that takes the values v on the
+ *      MRB is sum_i v_i g_i;
+ *   3. the candidates are, for every set e of at most k MRB indices, the
+ *      codeword with v_i = HD(llr_{b_i}) xor [i in e] (HD(l) = 1 iff l < 0).
+ *      They are numbered by |e| and then by the sorted index tuple of e in
+ *      lexicographic order;
+ *   4. the list is the L candidates of smallest metric (orc_metric), ties to
+ *      the smaller candidate number, in that order.
+ * anchors[L][N], metric[L] out; mrb[K] out (may be NULL).  Returns the
+ * number of list entries, min(L, number of candidates), or -1.              */
+double orc_metric(int mode, int n, const double* y, const uint8_t* c);
+
+typedef struct { double met; int64_t num; uint8_t* c; } osd_cand;
+
+static int cmp_osd(const void* a, const void* b)
+{
+    const osd_cand* x = (const osd_cand*)a;
+    const osd_cand* y = (const osd_cand*)b;
+    if (x->met != y->met) return x->met < y->met ? -1 : 1;
+    return x->num < y->num ? -1 : (x->num > y->num ? 1 : 0);
+}
+
+int orc_osd(int r, int m, int order, int L, int mode, const double* llr,
+            uint8_t* anchors, double* metric, int32_t* mrb_out)
+{
+    int n, K;
+    if (orc_rm_dims(r, m, &n, &K) != 0 || order < 0 || order > K || L < 1) return -1;
+    /* generator rows: row i of F^{(x)m} for the information positions */
+    int32_t* A = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    orc_rm_info_set(r, m, A);
+    uint8_t* G = (uint8_t*)malloc((size_t)K * n);
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j < n; ++j) G[(size_t)i * n + j] = (uint8_t)((j & ~A[i]) == 0);
+    /* 1. reliability order (selection by repeated scan: plain and slow) */
+    int* ord = (int*)malloc(sizeof(int) * (size_t)n);
+    uint8_t* used = (uint8_t*)calloc((size_t)n, 1);
+    for (int s = 0; s < n; ++s) {
+        int best = -1;
+        for (int j = 0; j < n; ++j) {
+            if (used[j]) continue;
+            if (best < 0 || fabs(llr[j]) > fabs(llr[best])) best = j;
+        }
+        used[best] = 1;
+        ord[s] = best;
+    }
+    /* 2. MRB by Gaussian elimination along the order */
+    int* mrb = (int*)malloc(sizeof(int) * (size_t)K);
+    int piv = 0;
+    for (int s = 0; s < n && piv < K; ++s) {
+        int j = ord[s], row = -1;
+        for (int i = piv; i < K; ++i) if (G[(size_t)i * n + j]) { row = i; break; }
+        if (row < 0) continue;  /* column j depends on the kept ones */
+        if (row != piv)
+            for (int t = 0; t < n; ++t) {
+                uint8_t x = G[(size_t)row * n + t];
+                G[(size_t)row * n + t] = G[(size_t)piv * n + t];
+                G[(size_t)piv * n + t] = x;
+            }
+        for (int i = 0; i < K; ++i)
+            if (i != piv && G[(size_t)i * n + j])
+                for (int t = 0; t < n; ++t) G[(size_t)i * n + t] ^= G[(size_t)piv * n + t];
+        mrb[piv++] = j;
+    }
+    if (mrb_out) for (int i = 0; i < K; ++i) mrb_out[i] = mrb[i];
+    /* 3. candidates, in their numbering */
+    int64_t C = 0;
+    for (int s = 0; s <= order; ++s) C += binom(K, s);
+    osd_cand* cand = (osd_cand*)malloc(sizeof(osd_cand) * (size_t)C);
+    uint8_t* store = (uint8_t*)malloc((size_t)C * n);
+    uint8_t* v = (uint8_t*)malloc((size_t)K);
+    int e[64];
+    int64_t num = 0;
+    for (int s = 0; s <= order; ++s) {
+        for (int t = 0; t < s; ++t) e[t] = t;  /* first tuple of size s */
+        for (;;) {
+            for (int i = 0; i < K; ++i) v[i] = (uint8_t)(llr[mrb[i]] < 0);
+            for (int t = 0; t < s; ++t) v[e[t]] ^= 1;
+            uint8_t* c = store + (size_t)num * n;
+            memset(c, 0, (size_t)n);
+            for (int i = 0; i < K; ++i)
+                if (v[i]) for (int t = 0; t < n; ++t) c[t] ^= G[(size_t)i * n + t];
+            cand[num].met = orc_metric(mode, n, llr, c);
+            cand[num].num = num;
+            cand[num].c = c;
+            ++num;
+            /* next tuple of size s in lexicographic order */
+            int t = s - 1;
+            while (t >= 0 && e[t] == K - s + t) --t;
+            if (t < 0) break;
+            ++e[t];
+            for (int u = t + 1; u < s; ++u) e[u] = e[u - 1] + 1;
+        }
+    }
+    /* 4. the L best */
+    qsort(cand, (size_t)C, sizeof(osd_cand), cmp_osd);
+    int nl = (int)(C < L ? C : L);
+    for (int k = 0; k < nl; ++k) {
+        memcpy(anchors + (size_t)k * n, cand[k].c, (size_t)n);
+        metric[k] = cand[k].met;
+    }
+    free(A); free(G); free(ord); free(used); free(mrb); free(cand); free(store); free(v);
+    return nl;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Metrics.  ED(c) = ||y - x(c)||^2 with x = 1 - 2c (Sec. II-B), summed in
  * index order.  In ORC_INT mode the decoder uses the exact integer metric
  * M(c) = sum_{j : c_j = 1} q_j, which differs from the squared distance to q
