@@ -12,8 +12,10 @@ Other workloads: --workload rm38 (RM(3,8), 32768 frames at 2.0 dB, L=16,
 T=12, 777240 moves), --workload mixed (262144 frames, RM(2,6) / RM(2,7)
 / RM(3,7) in equal shares at 2.5 dB, L=8, T=8, all codes' failing frames in
 one search launch per iteration), --workload rm26 (65536 RM(2,6) frames at
-3.0 dB, L=8, T=8, 2604 moves) and --workload rm26s2 (the same frames with the
-sphere of radius 2: 2604 + 291648 moves).
+3.0 dB, L=8, T=8, 2604 moves), --workload rm26s2 (the same frames with the
+sphere of radius 2: 2604 + 291648 moves) and --workload rm27osd (65536
+RM(2,7) frames at 2.5 dB without CRC, OSD(k) stage 1 with L=8 anchors, stage
+2 on every frame, T=4, 10668 moves).
 
 Prints one JSON line.  The roofline entry is for the stage-2 move-search
 kernel: dense int8 MFMA work 2 P N per searched path and iteration, over
@@ -43,7 +45,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed", "rm26", "rm26s2"])
+    ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed", "rm26", "rm26s2", "rm27osd"])
+    ap.add_argument("--osd-order", type=int, default=2, help="OSD order k of the rm27osd workload")
     ap.add_argument("--frames", type=int, default=0, help="override the workload's frame count")
     ap.add_argument("--ebn0", type=float, default=None, help="override the workload's Eb/N0")
     ap.add_argument("--seed", type=int, default=0)
@@ -57,8 +60,12 @@ def parse():
 
 
 def workload(args, synth):
-    """[(Workload, frames)], L, T, sphere radius of the move tables."""
-    if args.workload == "rm37":
+    """[(Workload, frames)], L, T, sphere radius of the move tables, OSD order
+    of stage 1 (None: SCL with the CRC)."""
+    if args.workload == "rm27osd":
+        wl = synth.Workload(r=2, m=7, k_pay=29, crc_len=0, ebn0_db=2.5, wid=4)
+        segs, L, T = [(wl, 65536)], 8, 4
+    elif args.workload == "rm37":
         segs, L, T = [(synth.RM37, 65536)], 8, 8
     elif args.workload == "rm38":
         segs, L, T = [(synth.RM38, 32768)], 16, 12
@@ -73,7 +80,8 @@ def workload(args, synth):
     if args.frames:
         segs = [(w, max(1, args.frames // len(segs))) for w, f in segs]
     radius = 2 if args.workload == "rm26s2" else 1
-    return segs, L, T, radius
+    osd = args.osd_order if args.workload == "rm27osd" else None
+    return segs, L, T, radius, osd
 
 
 def recorded_traffic(workload_name):
@@ -95,7 +103,7 @@ def recorded_traffic(workload_name):
     return int(m.group(3))
 
 
-def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1):
+def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1, osd=None):
     """The oracle on the first frames of every code's batch (the sample split
     evenly over the codes), int8 arithmetic, whole two-stage decode."""
     import oracle
@@ -107,8 +115,11 @@ def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1):
         parts.append("%d RM(%d,%d)" % (n, wl.r, wl.m))
     t0 = time.perf_counter()
     for (wl, F), q in zip(segs, qs):
-        oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads,
-                            radius=radius)
+        if osd is None:
+            oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, oracle.INT, q, threads=threads,
+                                radius=radius)
+        else:
+            oracle.decode_osd_batch(wl.r, wl.m, osd, L, T, oracle.INT, q, threads=threads, radius=radius)
     dt = time.perf_counter() - t0
     n = sum(len(q) for q in qs)
     return {"value": n / dt, "unit": "decoded frames/s", "cores": threads, "kind": "oracle",
@@ -128,7 +139,7 @@ def main():
     from paper_2602_08501_amd import decoder as D
     from paper_2602_08501_amd import synth
 
-    segs, L, T, radius = workload(args, synth)
+    segs, L, T, radius, osd = workload(args, synth)
     dev = "cuda:0"
     stream = torch.cuda.Stream()
     if args.calib_copy > 0:
@@ -155,22 +166,25 @@ def main():
 
     def stage1_all(raw=None):
         for i, (wl, F) in enumerate(segs):
-            if raw is None:
-                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], stream=stream)
-                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], stream=stream)
+            kw = {"stream": stream} if raw is None else {"raw_stream": raw}
+            D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], **kw)
+            if osd is None:
+                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], **kw)
             else:
-                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], raw_stream=raw)
-                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], raw_stream=raw)
+                D.stage1_osd(codes[i], osd, L, q_d[i], out=s1[i], **kw)
+
+    # OSD has no CRC: stage 2 runs on every frame (always-on mode)
+    crc_oks = [None if osd is not None else s["crc_ok"] for s in s1]
 
     def stage2(events=None, variant=-1, bpc=0, raw=None):
-        st.run(q_d, [s["anchors"] for s in s1], [s["crc_ok"] for s in s1], stream=None if raw else stream,
+        st.run(q_d, [s["anchors"] for s in s1], crc_oks, stream=None if raw else stream,
                events=events, variant=variant, blocks_per_cu=bpc, raw_stream=raw)
 
     with torch.cuda.stream(stream):
         stage1_all()
         stage2()
         torch.cuda.synchronize()
-        variant, bpc = autotune.tune(st, q_d, [s["anchors"] for s in s1], [s["crc_ok"] for s in s1], stream=stream)
+        variant, bpc = autotune.tune(st, q_d, [s["anchors"] for s in s1], crc_oks, stream=stream)
 
         # the whole step recorded once as a HIP graph, replayed per step
         def record(raw):
@@ -215,7 +229,7 @@ def main():
     per_seg_stats = []
     for i, (wl, F) in enumerate(segs if nseg > 1 else []):
         one = D.Stage2([(codes[i], F)], L, T, "i8", dev, want_moves=False)
-        one.run([q_d[i]], [s1[i]["anchors"]], [s1[i]["crc_ok"]])
+        one.run([q_d[i]], [s1[i]["anchors"]], [crc_oks[i]])
         torch.cuda.synchronize()
         per_seg_stats.append(one.stats.cpu().numpy().astype(np.int64))
     stats = st.stats.cpu().numpy()
@@ -223,16 +237,19 @@ def main():
         per_seg_stats = [stats.astype(np.int64)]
     per_seg_cols = [x[1:1 + T] for x in per_seg_stats]
     ed_units = [complexity.report(c.N, c.K, c.P, c.w, L, T, F, int(x[0]), x[1:1 + T].tolist(),
-                                  ms if nseg == 1 else None)
+                                  ms if nseg == 1 else None,
+                                  c_init=None if osd is None else float(complexity.c_osd(c.K, osd)))
                 for c, (_, F), x in zip(codes, segs, per_seg_stats)]
     dense_ops = sum(2.0 * c.P * c.N * cols for c, cols in zip(codes, per_seg_cols))  # per launch
     launches = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
                          for k in range(args.steps)]).mean(0)
     achieved = float(dense_ops.sum() / (launches.sum() * 1e-3) / 1e12)
-    fer = []
+    fer, fer1 = [], []
     for i in range(nseg):
         cw = np.unpackbits(st.outs[i]["cw"].cpu().numpy(), axis=-1, bitorder="little")
         fer.append(float((cw != txs[i]).any(1).mean()))
+        a0 = np.unpackbits(s1[i]["anchors"][:, 0].cpu().numpy(), axis=-1, bitorder="little")
+        fer1.append(float((a0 != txs[i]).any(1).mean()))
     move_evals = float(sum(c.P * cols.sum() for c, cols in zip(codes, per_seg_cols)))
     names = ["RM(%d,%d) N=%d P=%d%s Eb/N0 %.2f dB %d frames"
              % (w.r, w.m, c.N, c.P, " (sphere S_%d)" % radius if radius > 1 else "", w.ebn0_db, F)
@@ -250,9 +267,12 @@ def main():
         "vs_baseline": None,
         "dtype": "i8",
         "data": "synthetic (seeded BPSK/AWGN frames, random payloads)",
-        "config": {"workload": "; ".join(names) + "; int8 LLRs, SCL L=%d, T=%d" % (L, T),
+        "config": {"workload": "; ".join(names) + "; int8 LLRs, %s, T=%d"
+                               % ("SCL L=%d with CRC-6" % L if osd is None
+                                  else "OSD(%d) L=%d, no CRC, stage 2 always on" % (osd, L), T),
                    "frames": F_total, "stage2_frames": int(stats[0]), "p_act": int(stats[0]) / F_total,
-                   "paths_searched_per_iteration": stats[1:1 + T].tolist(), "fer": fer},
+                   "paths_searched_per_iteration": stats[1:1 + T].tolist(), "fer": fer,
+                   "fer_stage1_first_anchor": fer1},
         "stage2_move_evals_per_s": move_evals / (launches.sum() * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_INT8_DENSE_TOPS, "unit": "TOP/s",
                      "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(args.workload),
@@ -266,10 +286,10 @@ def main():
         "search_tiles": {"variant": variant, "blocks_per_cu": bpc, **_lib.mpwsd_search_variants()[variant]},
     }
     if args.cpu_frames < 0:
-        args.cpu_frames = {"rm38": 4096, "rm26s2": 8192}.get(args.workload, F_total)
+        args.cpu_frames = {"rm38": 4096, "rm26s2": 8192, "rm27osd": 16384}.get(args.workload, F_total)
     if args.cpu_frames > 0:
         thr = args.cpu_threads or min(16, os.cpu_count() or 1)
-        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr, radius)
+        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr, radius, osd)
     print(json.dumps(res))
 
 

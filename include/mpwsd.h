@@ -5,11 +5,12 @@
  * The decoder of Jo, Choi, Kim and Lee, "Multipoint Code-Weight Sphere
  * Decoding: Parallel Near-ML Decoding for Short-Blocklength Codes", for
  * Reed-Muller codes RM(r, m) with 5 <= m <= 8 (N = 2^m = 32 ... 256):
- *   stage 1 (Sec. III-A): successive-cancellation list decoding with a CRC;
- *   stage 2 (Sec. III-B, Alg. 1): for frames whose stage-1 CRC fails, L
- *     parallel greedy searches over the precomputed sphere S_1(0) (Eq. (3)),
- *     each scoring every move by its correlation gain (Eq. (5)), followed by
- *     the choice of the best path.
+ *   stage 1 (Sec. III-A): successive-cancellation list decoding with a CRC,
+ *     or ordered-statistics decoding of order k;
+ *   stage 2 (Sec. III-B, Alg. 1): for frames whose stage-1 CRC fails (or for
+ *     every frame, in the always-on mode), L parallel greedy searches over a
+ *     precomputed sphere S_rho(0) (Eq. (2)-(3)), each scoring every move by
+ *     its correlation gain (Eq. (5)), followed by the choice of the best path.
  *
  * Conventions shared by every call
  *   - Bit vectors are packed least-significant-bit first: bit j of a vector
@@ -83,7 +84,7 @@ int mpwsd_build_moves(int r, int m, uint8_t* moves, size_t cap_bytes,
  * weight is one of the `radius` smallest nonzero weights of the code (the
  * shells d_1 .. d_radius).  radius = 1 is mpwsd_build_moves.  For radius >= 2
  * the code must have dimension K <= 30 (the shells are found by visiting all
- * 2^K codewords on the host's threads; RM(2,7), K = 29, takes about a second).
+ * 2^K codewords on the host's threads; RM(2,7), K = 29, takes a few seconds).
  *
  * Rows are sorted by weight, then canonically as in mpwsd_build_moves, so the
  * first rows are the table of radius 1.  The stage-2 search treats every row
@@ -137,6 +138,39 @@ int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L,
                      const void* llr, int dtype, int64_t F,
                      uint8_t* anchors, uint8_t* crc_ok, int32_t* pm,
                      hipStream_t stream);
+
+/*
+ * mpwsd_stage1_osd - stage 1 by ordered-statistics decoding of order k
+ * (Sec. III-A; the OSD initialisation of Sec. IV-A, whose complexity is
+ * sum_{i<=k} C(K, i) candidates, Table I).  No CRC is involved: stage 2 then
+ * runs on every frame (always-on mode, Sec. III-C: pass crc_ok = NULL to
+ * mpwsd_decode_batch).
+ *
+ * Per frame:
+ *   1. positions ranked by reliability |llr_j|, largest first, ties to the
+ *      smaller position;
+ *   2. the most reliable basis: the first K positions in that order whose
+ *      generator columns are independent;
+ *   3. the candidates: for every set e of at most `order` basis indices, the
+ *      codeword that equals the hard decisions (HD(l) = 1 iff l < 0) on the
+ *      basis except at the indices in e; candidate numbers run by |e|, then
+ *      by the sorted index tuple of e in lexicographic order;
+ *   4. the anchors: the L candidates of smallest metric, ties to the smaller
+ *      candidate number, in ascending order.  Metric: int8 input M(c) =
+ *      sum_{c_j = 1} q_j (exact); float input ||y - x(c)||^2 in IEEE
+ *      binary32, summed in ascending position order without contraction.
+ *
+ * llr: device [F][N], int8 (MPWSD_I8) or float (MPWSD_F32), finite.
+ * anchors: device out [F][L][N/8] (bit j of a row is byte j/8, bit j%8).
+ * metric: device out [F][L] int32 (float input: the binary32 bit pattern),
+ *         or NULL.
+ * Supported: 5 <= m <= 8, 1 <= r < m, K <= 64, 0 <= order <= 4, 1 <= L <= 32,
+ * L <= sum_{i<=order} C(K, i), F <= INT_MAX.  Errors: MPWSD_ERR_UNSUPPORTED /
+ * MPWSD_ERR_ARG before anything is enqueued, MPWSD_ERR_DEVICE on a launch
+ * failure.
+ */
+int mpwsd_stage1_osd(int r, int m, int order, int L, const void* llr, int dtype, int64_t F,
+                     uint8_t* anchors, int32_t* metric, hipStream_t stream);
 
 /*
  * One group of frames of one code for stage 2.

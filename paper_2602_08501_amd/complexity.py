@@ -67,14 +67,15 @@ def c_mp_wsd(c_init: float, p_act: float, L_init: int, c_wsd_value: float) -> fl
 
 
 def report(N: int, K: int, S: int, w_bar: float, L: int, J: int, frames: int, stage2_frames: int,
-           paths_per_iteration, ms_per_step: float | None = None) -> dict:
-    """ED-unit accounting of one decoded batch with SCL(L) as stage 1.
+           paths_per_iteration, ms_per_step: float | None = None, c_init: float | None = None) -> dict:
+    """ED-unit accounting of one decoded batch.
 
-    paths_per_iteration[t] is the number of paths still searching at
-    iteration t over the whole batch; stage2_frames the frames that failed
-    the CRC (P_act = stage2_frames / frames)."""
+    Stage 1 costs c_init (default: SCL(L), C_scl).  paths_per_iteration[t] is
+    the number of paths still searching at iteration t over the whole batch;
+    stage2_frames the frames that went to stage 2 (P_act = stage2_frames /
+    frames: the CRC failures, or every frame in the always-on mode)."""
     p_act = stage2_frames / frames if frames else 0.0
-    init = c_scl(L, N)
+    init = c_scl(L, N) if c_init is None else c_init
     it = c_wsd_iteration(S, w_bar, N)
     worst = c_mp_wsd(init, p_act, L, J * it)
     searched = sum(int(n) for n in paths_per_iteration)
@@ -83,7 +84,7 @@ def report(N: int, K: int, S: int, w_bar: float, L: int, J: int, frames: int, st
     out = {
         "ed_unit_flops": ed_unit_flops(N),
         "filter_m": filter_size(S),
-        "c_scl": init,
+        "c_init": init,
         "c_wsd_eq6": J * it,
         "p_act": p_act,
         "c_mp_wsd_eq7": worst,

@@ -1,0 +1,412 @@
+// Stage 1 by ordered-statistics decoding of order k (Sec. III-A; the OSD
+// initialisation of the RM experiment, Sec. IV-A): per frame, the L
+// candidates of smallest metric become the anchors of stage 2, which then
+// runs on every frame (always-on mode, Sec. III-C).
+//
+// One wavefront per frame (workgroup of 64 lanes):
+//   1. reliability order: every position's rank is the number of positions
+//      with a smaller key (|llr| descending, then position), counted against
+//      all keys in LDS; position j is written to slot rank(j);
+//   2. most reliable basis: lane i holds generator row i (row A[i] of
+//      F^{(x)m}, bit-packed).  Positions are visited in reliability order;
+//      a ballot finds the unpivoted rows with a 1 there, the lowest such
+//      lane becomes the pivot, its row is broadcast and cleared from every
+//      other row holding a 1 there (Gauss-Jordan).  After K pivots row t is
+//      the codeword that is 1 at the t-th basis position and 0 at the others;
+//   3. candidates: for every set e of at most k basis indices (numbered by
+//      |e|, then lexicographically), c(e) = c0 xor sum_{i in e} g_i, c0 the
+//      codeword agreeing with the hard decisions on the basis.  The lanes
+//      split the numbering into 64 contiguous ranges.  Integer metric
+//      M(c) = sum_{c_j = 1} q_j from eight bit planes of q (ballots), one
+//      AND + popcount per plane and word; binary32 metric ||y - x(c)||^2
+//      summed in ascending position order;
+//   4. every lane keeps its L best (metric, number) keys in LDS; L rounds of
+//      a wave-wide minimum merge them, and lanes 0..L-1 rebuild and store the
+//      winners.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstring>
+
+#include "common.h"
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int MAXN = 256;
+constexpr int MAXK = 64;
+constexpr int MAX_ORDER = 4;
+
+__device__ __host__ inline uint32_t binom_small(int n, int k)
+{
+    // C(n, k) for 0 <= k <= 4, n <= 64 (fits 32 bits)
+    if (k < 0 || n < k) return 0;
+    switch (k) {
+    case 0: return 1;
+    case 1: return (uint32_t)n;
+    case 2: return (uint32_t)n * (n - 1) / 2;
+    case 3: return (uint32_t)n * (n - 1) * (n - 2) / 6;
+    default: return (uint32_t)n * (n - 1) * (n - 2) * (n - 3) / 24;
+    }
+}
+
+// Set of j in [0, 64) with j a subset of a (bitwise): the low word of row a of F^{(x)6}.
+__device__ inline uint64_t subset_mask64(uint32_t a)
+{
+    uint64_t mk = 1;
+    for (int t = 0; t < 6; ++t)
+        if ((a >> t) & 1u) mk |= mk << (1 << t);
+    return mk;
+}
+
+// Value of lane `src` (wave-uniform) to every lane, through scalar registers.
+__device__ inline uint64_t readlane_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// v combined with the value of a partner lane inside its row of 16 (DPP).
+template <int CTRL>
+__device__ inline uint64_t dpp_partner(uint64_t v)
+{
+    const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)v, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(v >> 32), (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+constexpr int DPP_QUAD_1032 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141; // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;      // lane i <-> 15 - i within 16
+
+// Minimum over the wave: inside each row of 16 lanes by DPP, then across the
+// four rows through scalar reads.  Every lane returns the minimum.
+__device__ inline uint64_t wave_min_u64(uint64_t v)
+{
+    uint64_t o;
+    o = dpp_partner<DPP_QUAD_1032>(v); v = o < v ? o : v;
+    o = dpp_partner<DPP_QUAD_2301>(v); v = o < v ? o : v;
+    o = dpp_partner<DPP_HALF_MIRROR>(v); v = o < v ? o : v;
+    o = dpp_partner<DPP_MIRROR>(v); v = o < v ? o : v;
+    const uint64_t a = readlane_u64(v, 0), b = readlane_u64(v, 16), c = readlane_u64(v, 32), d = readlane_u64(v, 48);
+    const uint64_t ab = a < b ? a : b, cd = c < d ? c : d;
+    return ab < cd ? ab : cd;
+}
+
+// Exclusive-or over the wave, returned to every lane.
+__device__ inline uint64_t wave_xor_u64(uint64_t v)
+{
+    v ^= dpp_partner<DPP_QUAD_1032>(v);
+    v ^= dpp_partner<DPP_QUAD_2301>(v);
+    v ^= dpp_partner<DPP_HALF_MIRROR>(v);
+    v ^= dpp_partner<DPP_MIRROR>(v);
+    return readlane_u64(v, 0) ^ readlane_u64(v, 16) ^ readlane_u64(v, 32) ^ readlane_u64(v, 48);
+}
+
+// Pattern e = {e_0 < e_1 < ...} of size s (s <= 4), one byte per element.
+struct Pattern {
+    int s;
+    uint32_t e;
+    __device__ int at(int t) const { return (int)((e >> (8 * t)) & 0xFFu); }
+    __device__ void set(int t, int v) { e = (e & ~(0xFFu << (8 * t))) | ((uint32_t)v << (8 * t)); }
+};
+
+// Candidate number -> pattern (numbering: by size, then lexicographic).
+__device__ inline Pattern unrank(uint32_t num, int K)
+{
+    Pattern p{0, 0};
+    int s = 0;
+    while (num >= binom_small(K, s)) {
+        num -= binom_small(K, s);
+        ++s;
+    }
+    p.s = s;
+    int x = 0;
+    for (int t = 0; t < s; ++t) {
+        for (;;) {
+            const uint32_t cnt = binom_small(K - 1 - x, s - 1 - t);
+            if (num < cnt) break;
+            num -= cnt;
+            ++x;
+        }
+        p.set(t, x);
+        ++x;
+    }
+    return p;
+}
+
+// The pattern numbered one higher.
+__device__ inline void next_pattern(Pattern& p, int K)
+{
+    int t = p.s - 1;
+    while (t >= 0 && p.at(t) == K - p.s + t) --t;
+    if (t < 0) {
+        ++p.s;
+        p.e = 0;
+        for (int u = 0; u < p.s; ++u) p.set(u, u);
+        return;
+    }
+    const int v = p.at(t) + 1;
+    p.set(t, v);
+    for (int u = t + 1; u < p.s; ++u) p.set(u, v + (u - t));
+}
+
+template <int W>
+__device__ inline void build_candidate(uint64_t (&c)[W], const uint64_t (&c0)[W], const uint64_t* rows, const Pattern& p)
+{
+#pragma unroll
+    for (int w = 0; w < W; ++w) c[w] = c0[w];
+    for (int t = 0; t < p.s; ++t) {
+        const uint64_t* g = rows + (size_t)p.at(t) * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w) c[w] ^= g[w];
+    }
+}
+
+// W: 64-bit words per codeword (N = 32 uses the low half of one word).
+template <int W, bool FLOAT>
+__global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr, int64_t F, int m, int r, int K,
+                                                   int order, int L, uint8_t* __restrict__ anchors,
+                                                   int32_t* __restrict__ metric_out)
+{
+    const int N = 1 << m;
+    const int NB = N / 8;
+    const int lane = threadIdx.x;
+    const int64_t f = blockIdx.x;
+    if (f >= F) return;  // whole workgroup: no barrier is skipped by part of it
+
+    __shared__ float ys[FLOAT ? MAXN : 1];
+    __shared__ int8_t qs[MAXN];
+    __shared__ uint64_t keys[MAXN];
+    __shared__ uint16_t sorted[MAXN];
+    __shared__ uint16_t info[MAXK];
+    __shared__ uint16_t mrb[MAXK];
+    __shared__ uint64_t rows[MAXK * W];
+    __shared__ uint64_t c0s[W];
+    __shared__ uint64_t win[32];
+    extern __shared__ uint64_t lists[];  // [L][64]
+
+    // ---- 1. channel values and reliability keys
+    for (int j = lane; j < N; j += WAVE) {
+        uint32_t mag;
+        if (FLOAT) {
+            const float v = ((const float*)llr)[f * N + j];
+            ys[j] = v;
+            qs[j] = v < 0.0f ? -1 : 0;  // hard decision only
+            mag = __float_as_uint(fabsf(v));
+        } else {
+            const int8_t v = ((const int8_t*)llr)[f * N + j];
+            qs[j] = v;
+            mag = (uint32_t)(v < 0 ? -(int)v : (int)v);
+        }
+        keys[j] = ((uint64_t)(0xFFFFFFFFu - mag) << 32) | (uint32_t)j;
+    }
+    __syncthreads();
+    for (int j = lane; j < N; j += WAVE) {
+        const uint64_t kj = keys[j];
+        int rank = 0;
+        for (int i = 0; i < N; ++i) rank += keys[i] < kj;
+        sorted[rank] = (uint16_t)j;
+    }
+    // information set A = {i : popcount(i) >= m - r}, ascending (compaction by ballot)
+    {
+        int base = 0;
+        for (int h = 0; h * WAVE < N; ++h) {
+            const int j = h * WAVE + lane;
+            const bool fl = j < N && __popc((unsigned)j) >= m - r;
+            const uint64_t bal = __ballot(fl);
+            if (fl) info[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)j;
+            base += __popcll(bal);
+        }
+    }
+    __syncthreads();
+
+    // ---- 2. most reliable basis by Gauss-Jordan elimination, one row per lane
+    uint64_t row[W];
+    {
+        const uint32_t a = lane < K ? info[lane] : 0;
+        const uint64_t low = subset_mask64(a & 63u);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            row[w] = (lane < K && (((uint32_t)w & ~(a >> 6)) == 0)) ? low : 0;
+    }
+    bool pivoted = false;
+    int pivnum = 0;
+    int count = 0;
+    for (int s = 0; s < N && count < K; ++s) {
+        const int j = __builtin_amdgcn_readfirstlane((int)sorted[s]);
+        const int ws = j >> 6, bs = j & 63;
+        uint64_t rw = row[0];
+#pragma unroll
+        for (int w = 1; w < W; ++w)
+            if (ws == w) rw = row[w];
+        const bool bit = (rw >> bs) & 1ull;
+        const uint64_t cand = __ballot(bit && !pivoted);
+        if (cand == 0) continue;  // column j depends on the basis so far
+        const int p = __builtin_ctzll(cand);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t pr = readlane_u64(row[w], p);
+            if (bit && lane != p) row[w] ^= pr;
+        }
+        if (lane == p) {
+            pivoted = true;
+            pivnum = count;
+        }
+        if (lane == 0) mrb[count] = (uint16_t)j;
+        ++count;
+    }
+    if (pivoted)
+#pragma unroll
+        for (int w = 0; w < W; ++w) rows[pivnum * W + w] = row[w];
+    __syncthreads();
+
+    // c0: the codeword with the hard decisions on the basis
+    {
+        bool hd = false;
+        if (lane < K) hd = qs[mrb[lane]] < 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const uint64_t v = wave_xor_u64((lane < K && hd) ? rows[lane * W + w] : 0);
+            if (lane == 0) c0s[w] = v;
+        }
+    }
+    __syncthreads();
+    uint64_t c0[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) c0[w] = c0s[w];
+
+    // bit planes of q (integer metric)
+    uint64_t plane[FLOAT ? 1 : W][8];
+    if (!FLOAT) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int j = w * WAVE + lane;
+            const uint32_t qb = j < N ? (uint32_t)(uint8_t)qs[j] : 0u;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) plane[w][b] = __ballot((qb >> b) & 1u);
+        }
+    }
+
+    // ---- 3. candidates of this lane's range, best L kept in LDS
+    uint32_t C = 0;
+    for (int s = 0; s <= order; ++s) C += binom_small(K, s);
+    const uint32_t lo = (uint32_t)((uint64_t)C * lane / WAVE), hi = (uint32_t)((uint64_t)C * (lane + 1) / WAVE);
+    int cnt = 0;
+    uint64_t thr = ~0ull;
+    if (lo < hi) {
+        Pattern p = unrank(lo, K);
+        for (uint32_t num = lo; num < hi; ++num) {
+            uint64_t c[W];
+            build_candidate<W>(c, c0, rows, p);
+            uint32_t mk;
+            if (FLOAT) {
+                float e = 0.0f;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const uint64_t cw = c[w];
+                    const int nb = N - 64 * w < 64 ? N - 64 * w : 64;
+                    for (int b = 0; b < nb; ++b) {
+                        const float x = ((cw >> b) & 1ull) ? -1.0f : 1.0f;
+                        const float d = __fsub_rn(ys[64 * w + b], x);
+                        e = __fadd_rn(e, __fmul_rn(d, d));
+                    }
+                }
+                mk = __float_as_uint(e);  // e >= 0: bits are monotone
+            } else {
+                int M = 0;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    int pc = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) pc += __popcll(c[w] & plane[FLOAT ? 0 : w][b]);
+                    M += (b == 7 ? -128 : (1 << b)) * pc;
+                }
+                mk = (uint32_t)M ^ 0x80000000u;  // order-preserving for int32
+            }
+            const uint64_t key = ((uint64_t)mk << 32) | num;
+            if (key < thr) {
+                int pos = cnt < L ? cnt : L - 1;
+                while (pos > 0 && lists[(pos - 1) * WAVE + lane] > key) {
+                    lists[pos * WAVE + lane] = lists[(pos - 1) * WAVE + lane];
+                    --pos;
+                }
+                lists[pos * WAVE + lane] = key;
+                if (cnt < L) ++cnt;
+                if (cnt == L) thr = lists[(L - 1) * WAVE + lane];
+            }
+            if (num + 1 < hi) next_pattern(p, K);
+        }
+    }
+
+    // ---- 4. L rounds of a wave minimum over the lanes' list heads
+    int head = 0;
+    for (int t = 0; t < L; ++t) {
+        const uint64_t mine = head < cnt ? lists[head * WAVE + lane] : ~0ull;
+        const uint64_t best = wave_min_u64(mine);
+        if (mine == best && best != ~0ull) ++head;
+        if (lane == 0) win[t] = best;
+    }
+    __syncthreads();
+    if (lane < L) {
+        const uint64_t key = win[lane];
+        const Pattern p = unrank((uint32_t)key, K);
+        uint64_t c[W];
+        build_candidate<W>(c, c0, rows, p);
+        uint8_t* dst = anchors + ((size_t)f * L + lane) * NB;
+        for (int b = 0; b < NB; ++b) dst[b] = (uint8_t)(c[b >> 3] >> (8 * (b & 7)));
+        if (metric_out) {
+            const uint32_t mk = (uint32_t)(key >> 32);
+            metric_out[f * L + lane] = FLOAT ? (int32_t)mk : (int32_t)(mk ^ 0x80000000u);
+        }
+    }
+}
+
+template <int W>
+void launch_w(bool fl, const void* llr, int64_t F, int m, int r, int K, int order, int L, uint8_t* anchors,
+              int32_t* metric, hipStream_t s)
+{
+    const size_t lds = (size_t)L * WAVE * sizeof(uint64_t);
+    if (fl)
+        hipLaunchKernelGGL((osd_kernel<W, true>), dim3((unsigned)F), dim3(WAVE), lds, s, llr, F, m, r, K, order, L,
+                           anchors, metric);
+    else
+        hipLaunchKernelGGL((osd_kernel<W, false>), dim3((unsigned)F), dim3(WAVE), lds, s, llr, F, m, r, K, order,
+                           L, anchors, metric);
+}
+
+}  // namespace
+
+extern "C" int mpwsd_stage1_osd(int r, int m, int order, int L, const void* llr, int dtype, int64_t F,
+                                uint8_t* anchors, int32_t* metric, hipStream_t stream)
+{
+    using mpwsd::fail;
+    mpwsd::clear_error();
+    if (m < 5 || m > 8 || r < 1 || r >= m)
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_osd: need 1 <= r < m, 5 <= m <= 8 (r=%d m=%d)", r, m);
+    const int K = mpwsd::rm_dimension(r, m);
+    if (K > MAXK) return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_osd: K=%d exceeds %d", K, MAXK);
+    if (order < 0 || order > MAX_ORDER)
+        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_osd: order must be in [0, %d] (got %d)", MAX_ORDER, order);
+    if (L < 1 || L > 32) return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_osd: need 1 <= L <= 32 (L=%d)", L);
+    uint32_t C = 0;
+    for (int s = 0; s <= order; ++s) C += binom_small(K, s);
+    if ((uint32_t)L > C)
+        return fail(MPWSD_ERR_ARG, "mpwsd_stage1_osd: L=%d exceeds the %u candidates of order %d", L, C, order);
+    if (dtype != MPWSD_I8 && dtype != MPWSD_F32) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_osd: bad dtype %d", dtype);
+    if (F < 0 || F > INT_MAX) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_osd: F=%lld out of range", (long long)F);
+    if (F == 0) return MPWSD_OK;
+    if (!llr || !anchors) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_osd: null pointer");
+    const bool fl = dtype == MPWSD_F32;
+    switch (m) {
+    case 5:
+    case 6: launch_w<1>(fl, llr, F, m, r, K, order, L, anchors, metric, stream); break;
+    case 7: launch_w<2>(fl, llr, F, m, r, K, order, L, anchors, metric, stream); break;
+    default: launch_w<4>(fl, llr, F, m, r, K, order, L, anchors, metric, stream); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MPWSD_ERR_DEVICE, "mpwsd_stage1_osd: %s", hipGetErrorString(e));
+    return MPWSD_OK;
+}

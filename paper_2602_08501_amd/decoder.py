@@ -92,6 +92,22 @@ def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: in
     return out
 
 
+def stage1_osd(code: Code, order: int, L: int, llr: torch.Tensor, out=None, stream=None, want_metric: bool = False,
+               raw_stream=None):
+    """OSD(order) anchors of every frame, smallest metric first (no CRC: run
+    stage 2 with crc_ok None, the always-on mode)."""
+    F = llr.shape[0]
+    dev = llr.device
+    if out is None:
+        out = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev)}
+        if want_metric:
+            out["metric"] = torch.empty((F, L), dtype=torch.int32, device=dev)
+    dtype = MPWSD_I8 if llr.dtype == torch.int8 else MPWSD_F32
+    check(_lib.mpwsd_stage1_osd(code.r, code.m, order, L, llr.data_ptr(), dtype, F, out["anchors"].data_ptr(),
+                                _ptr(out.get("metric")), raw_stream if raw_stream is not None else _stream(stream)))
+    return out
+
+
 class Stage2:
     """Buffers and one call of mpwsd_decode_batch for a fixed batch shape."""
 

@@ -15,6 +15,7 @@ def test_library_exports_every_declared_call():
     lib = _lib.load()
     names = _lib.header_functions()
     assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_quantize_llr",
+                          "mpwsd_stage1_osd",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
                           "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy",
@@ -178,3 +179,28 @@ def test_server_argument_errors():
     assert lib.mpwsd_server_create(arr, 1, 0x10010, need, ctypes.byref(h)) == _lib.MPWSD_ERR_ARG
     assert lib.mpwsd_server_tick(None, None) == _lib.MPWSD_ERR_ARG
     assert lib.mpwsd_server_destroy(None) == 0
+
+
+def test_stage1_osd_validates_before_enqueue():
+    A = 0x1000
+    base = dict(r=2, m=7, order=2, L=8, llr=A, dtype=0, F=4, anchors=A, metric=None)
+    cases = [
+        (dict(m=9), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(r=4, m=8), _lib.MPWSD_ERR_UNSUPPORTED),      # K = 163 > 64
+        (dict(order=5), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(order=-1), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(L=33), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(L=0), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(order=0, L=2), _lib.MPWSD_ERR_ARG),          # one candidate only
+        (dict(dtype=3), _lib.MPWSD_ERR_ARG),
+        (dict(F=-1), _lib.MPWSD_ERR_ARG),
+        (dict(llr=None), _lib.MPWSD_ERR_ARG),
+        (dict(anchors=None), _lib.MPWSD_ERR_ARG),
+    ]
+    for kw, code in cases:
+        a = dict(base, **kw)
+        rc = _lib.mpwsd_stage1_osd(a["r"], a["m"], a["order"], a["L"], a["llr"], a["dtype"], a["F"],
+                                   a["anchors"], a["metric"], None)
+        assert rc == code, (kw, rc, _lib.last_error())
+    # F = 0 is a no-op that needs no pointers
+    assert _lib.mpwsd_stage1_osd(2, 7, 2, 8, None, 0, 0, None, None, None) == 0

@@ -59,9 +59,18 @@ def test_report_consistency():
                  paths_per_iteration=[400, 300, 100, 0, 0, 0, 0, 0], ms_per_step=0.5)
     assert r["p_act"] == 0.05
     it = C.c_wsd_iteration(94488, 16, 128)
+    assert r["c_init"] == C.c_scl(8, 128)
     assert r["c_mp_wsd_eq7"] == pytest.approx(C.c_scl(8, 128) + 0.05 * 8 * 8 * it)
     # measured activity (800 path-iterations) is below the worst case (50 * 8 * 8 = 3200)
     assert r["c_mp_wsd_measured_activity"] == pytest.approx(C.c_scl(8, 128) + 0.8 * it)
     assert r["c_mp_wsd_measured_activity"] < r["c_mp_wsd_eq7"]
     assert r["dense_search_ed_units_per_path_iteration"] == pytest.approx(2 * 94488 / 3)
     assert r["ns_per_frame"] == pytest.approx(500.0)
+
+
+def test_report_osd_always_on():
+    # OSD(2) on RM(2,7): C_osd = 1 + 29 + 406 = 436; always on: P_act = 1
+    r = C.report(N=128, K=29, S=10668, w_bar=32, L=8, J=4, frames=10, stage2_frames=10,
+                 paths_per_iteration=[80, 20, 5, 0], c_init=float(C.c_osd(29, 2)))
+    assert r["c_init"] == 436 and r["p_act"] == 1.0
+    assert r["c_mp_wsd_eq7"] == pytest.approx(436 + 8 * C.c_wsd(4, 10668, 32, 128))

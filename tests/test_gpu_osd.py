@@ -1,0 +1,131 @@
+"""GPU parity of the OSD(k) stage 1 (mpwsd_stage1_osd) and of OSD + the
+always-on stage 2, through the C-ABI, against the oracle on the same seeded
+frames: anchors and their metrics bit-exactly (int8 and binary32), then the
+whole decode (decisions, chosen paths, metrics, every logged move)."""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_08501_amd import decoder as D
+from paper_2602_08501_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+_codes = {}
+
+
+def code(r, m):
+    if (r, m) not in _codes:
+        _codes[(r, m)] = D.Code(r, m, DEV)
+    return _codes[(r, m)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def unpack(t):
+    return np.unpackbits(t.cpu().numpy(), axis=-1, bitorder="little")
+
+
+def frames(r, m, ebn0, F, wid, seed=0):
+    N = 1 << m
+    K = oracle.rm_dims(r, m)[1]
+    wl = synth.Workload(r=r, m=m, k_pay=K, crc_len=0, ebn0_db=ebn0, wid=wid)
+    pay, c, y = synth.generate(wl, seed, 0, F)
+    return wl, c, y, oracle.quantize(y, wl.llr_scale)
+
+
+# (name, r, m, order, L, Eb/N0, frames)
+ANCHOR_CASES = [
+    ("rm27_k2_L8", 2, 7, 2, 8, 2.0, 192),
+    ("rm27_k3_L16", 2, 7, 3, 16, 2.5, 96),
+    ("rm26_k4_L32", 2, 6, 4, 32, 2.0, 64),
+    ("rm15_k4_L32", 1, 5, 4, 32, 0.0, 64),
+    ("rm37_K64_k1_L8", 3, 7, 1, 8, 2.0, 64),
+    ("rm28_N256_k2_L4", 2, 8, 2, 4, 2.0, 48),
+    ("rm27_k0_L1", 2, 7, 0, 1, 2.0, 64),
+]
+
+
+@pytest.mark.parametrize("name,r,m,order,L,ebn0,F", ANCHOR_CASES, ids=[c[0] for c in ANCHOR_CASES])
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_osd_anchor_parity(name, r, m, order, L, ebn0, F, dtype):
+    say("case: osd anchors", name, dtype)
+    wl, c, y, q = frames(r, m, ebn0, F, wid=30 + m)
+    obs = q if dtype == "i8" else y
+    out = D.stage1_osd(code(r, m), order, L, torch.from_numpy(obs).to(DEV), want_metric=True)
+    torch.cuda.synchronize()
+    anc = unpack(out["anchors"])
+    met = out["metric"].cpu().numpy()
+    mode = oracle.INT if dtype == "i8" else oracle.F32
+    for f in range(F):
+        a, om, _ = oracle.osd(r, m, order, L, mode, obs[f].astype(np.float64))
+        assert np.array_equal(anc[f], a), f
+        if dtype == "i8":
+            assert np.array_equal(met[f], om.astype(np.int32)), f
+        else:
+            assert np.array_equal(met[f].view(np.float32), om.astype(np.float32)), f
+
+
+def test_osd_ties_follow_candidate_numbering():
+    """All-zero and constant-magnitude LLRs: every reliability ties (order by
+    position) and, for zeros, every metric ties (order by candidate number)."""
+    r, m, order, L = 2, 6, 2, 32
+    N = 64
+    obs = np.zeros((4, N), np.int8)
+    obs[1] = 5
+    obs[2] = -5
+    obs[3, ::2] = 7
+    obs[3, 1::2] = -7
+    out = D.stage1_osd(code(r, m), order, L, torch.from_numpy(obs).to(DEV), want_metric=True)
+    torch.cuda.synchronize()
+    anc = unpack(out["anchors"])
+    for f in range(len(obs)):
+        a, om, _ = oracle.osd(r, m, order, L, oracle.INT, obs[f].astype(np.float64))
+        assert np.array_equal(anc[f], a), f
+        assert np.array_equal(out["metric"].cpu().numpy()[f], om.astype(np.int32))
+
+
+DECODE_CASES = [
+    ("rm27_k2_L8_T4", 2, 7, 2, 8, 4, 2.0, 160),
+    ("rm27_k3_L4_T4", 2, 7, 3, 4, 4, 2.5, 96),
+    ("rm26_k2_L8_T4_r2", 2, 6, 2, 8, 4, 1.5, 96),
+]
+
+
+@pytest.mark.parametrize("name,r,m,order,L,T,ebn0,F", DECODE_CASES, ids=[c[0] for c in DECODE_CASES])
+@pytest.mark.parametrize("dtype", ["i8", "f32"])
+def test_osd_always_on_decode_parity(name, r, m, order, L, T, ebn0, F, dtype):
+    say("case: osd + always-on decode", name, dtype)
+    radius = 2 if name.endswith("_r2") else 1
+    wl, c, y, q = frames(r, m, ebn0, F, wid=40 + m)
+    obs = q if dtype == "i8" else y
+    cd = D.Code(r, m, DEV, radius=radius)
+    llr = torch.from_numpy(obs).to(DEV)
+    s1 = D.stage1_osd(cd, order, L, llr)
+    st = D.Stage2([(cd, F)], L, T, dtype, DEV)
+    out = st.run([llr], [s1["anchors"]], [None])[0]
+    torch.cuda.synchronize()
+    stats = st.stats.cpu().numpy()
+    mode = oracle.INT if dtype == "i8" else oracle.F32
+    ref = oracle.decode_osd_batch(r, m, order, L, T, mode, obs.astype(np.float64), threads=8, radius=radius)
+    assert np.array_equal(unpack(s1["anchors"]), ref["anchors"])
+    assert stats[0] == F and stats[1] == F * L          # always on: every frame, every path
+    assert np.array_equal(out["moves"].cpu().numpy(), ref["logs"])
+    assert np.array_equal(unpack(out["cw"]), ref["c"])
+    assert np.array_equal(out["k"].cpu().numpy(), ref["k"])
+    met = out["metric"].cpu().numpy()
+    if dtype == "i8":
+        assert np.array_equal(met, ref["metric"].astype(np.int32))
+    else:
+        assert np.array_equal(met.view(np.float32), ref["metric"].astype(np.float32))
+    fer_anchor = float((ref["anchors"][:, 0] != c).any(1).mean())
+    fer = float((ref["c"] != c).any(1).mean())
+    say("  FER OSD alone %.3f, with MP-WSD %.3f" % (fer_anchor, fer))
+    assert fer <= fer_anchor
