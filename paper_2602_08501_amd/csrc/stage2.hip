@@ -276,7 +276,9 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
     constexpr int NT = NWAVES * WAVE;
     constexpr int NB = N / 8;                   // packed bytes per move
     constexpr int UW = N / 32;                  // 32-bit units per move
-    int8_t* buf[2] = {lds, lds + RC * RS};
+    // chunk buffer b (0 or 1); computed from lds at every use so the compiler
+    // keeps the LDS address space (ds_read/ds_write, not flat accesses)
+    auto buf = [lds](int b) { return lds + b * (RC * RS); };
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -284,7 +286,7 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
 
     if (N < KP) {  // positions >= N stay zero
         for (int e = tid; e < 2 * RC; e += NT) {
-            int8_t* row = buf[e / RC] + (e % RC) * RS;
+            int8_t* row = buf(e / RC) + (e % RC) * RS;
             for (int j = N; j < KP; j += 16) *(v4i*)(row + j) = v4i{0, 0, 0, 0};
         }
     }
@@ -312,7 +314,7 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
                 const int row = u / UW, wd = u % UW;
                 uint32_t o[8];
                 unpack32(reg[r], o);
-                int8_t* dst = buf[b] + row * RS + 32 * wd;
+                int8_t* dst = buf(b) + row * RS + 32 * wd;
                 *(v4i*)(dst) = v4i{(int)o[0], (int)o[1], (int)o[2], (int)o[3]};
                 *(v4i*)(dst + 16) = v4i{(int)o[4], (int)o[5], (int)o[6], (int)o[7]};
             }
@@ -354,7 +356,7 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
 #pragma unroll 2
         for (int tt = 0; tt < RC / 16; ++tt) {
             v4i af[HK];
-            const int8_t* src = buf[b] + (tt * 16 + li) * RS + lg * (KP / 4);
+            const int8_t* src = buf(b) + (tt * 16 + li) * RS + lg * (KP / 4);
 #pragma unroll
             for (int h = 0; h < HK; ++h) af[h] = *(const v4i*)(src + 16 * h);
             // accumulator seed: the row's index within the chunk
@@ -370,7 +372,10 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
                 for (int c = 0; c < NC; ++c) acc[c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[h], zf[c][h], acc[c], 0, 0, 0);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {  // two v_min3 per four values
-                const int t3 = min(min(acc[c][0], acc[c][1]), acc[c][2]);
+                int t3 = min(min(acc[c][0], acc[c][1]), acc[c][2]);
+                // keeps the compiler from rebalancing the two minima into three
+                // instructions that each read matrix-core results
+                asm volatile("" : "+v"(t3));
                 cm[c] = min(min(cm[c], t3), acc[c][3]);
             }
         }
