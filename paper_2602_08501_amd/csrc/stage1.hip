@@ -45,6 +45,39 @@ template <typename V> __device__ inline V f_minsum(V a, V b)
     return ((a < 0) != (b < 0)) ? -m : m;
 }
 
+// Packed int16 helpers (two 16-bit lanes per 32-bit register; integer ops,
+// no floating point involved).
+typedef short short2_t __attribute__((ext_vector_type(2)));
+__device__ inline short2_t as_s2(uint32_t x) { return __builtin_bit_cast(short2_t, x); }
+__device__ inline uint32_t as_u(short2_t x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ inline uint32_t pk_add_u16(uint32_t a, uint32_t b) { return as_u(as_s2(a) + as_s2(b)); }
+__device__ inline uint32_t pk_sub_u16(uint32_t a, uint32_t b) { return as_u(as_s2(a) - as_s2(b)); }
+__device__ inline uint32_t pk_ashr15(uint32_t a) { return as_u(as_s2(a) >> (short2_t){15, 15}); }
+__device__ inline uint32_t pk_min_i16(uint32_t a, uint32_t b)
+{
+    const short2_t x = as_s2(a), y = as_s2(b);
+    return as_u(x < y ? x : y);
+}
+__device__ inline uint32_t pk_max_i16(uint32_t a, uint32_t b)
+{
+    const short2_t x = as_s2(a), y = as_s2(b);
+    return as_u(x > y ? x : y);
+}
+__device__ inline uint32_t pk_abs_i16(uint32_t a) { return pk_max_i16(a, pk_sub_u16(0u, a)); }
+// min-sum f on both halves: sgn(a) sgn(b) min(|a|, |b|)
+__device__ inline uint32_t f_pk(uint32_t a, uint32_t b)
+{
+    const uint32_t sg = pk_ashr15(a ^ b);
+    const uint32_t mn = pk_min_i16(pk_abs_i16(a), pk_abs_i16(b));
+    return pk_sub_u16(mn ^ sg, sg);
+}
+// g on both halves: b + (1 - 2 v) a, v = bit 0 (low half) / bit 1 (high half)
+__device__ inline uint32_t g_pk(uint32_t a, uint32_t b, uint32_t bits2)
+{
+    const uint32_t m = ((bits2 & 1u) ? 0x0000FFFFu : 0u) | ((bits2 & 2u) ? 0xFFFF0000u : 0u);
+    return pk_add_u16(b, pk_sub_u16(a ^ m, m));
+}
+
 // Polar transform x -> x F^{(x)lev} of the n = 2^lev bits held in w[]
 // (bit k of position k, 32 per word): within-word butterflies for the first
 // five factors, whole-word xors for the rest.
@@ -85,11 +118,19 @@ template <int M, int L, bool FLOAT> struct Scl {
     static constexpr int N = 1 << M;
     static constexpr int NW = N / 32;    // words of decided bits per path
     static constexpr int G = WAVE / L;   // frames per wave
+    // channel row stride: an odd number of 32-bit words, so the G frames'
+    // rows start in different LDS banks
+    static constexpr int CHS = N + (sizeof(S) == 2 ? 2 : 1);
     using Key = typename std::conditional<FLOAT, uint64_t, uint32_t>::type;
 
     struct Smem {
-        S buf[(N - 1) * WAVE];  // level l of lane x: rows [2^l - 1, 2^(l+1) - 1), column x
-        S ch[G * N];            // channel LLRs of the wave's frames
+        // level l of lane x.  Float: rows [2^l - 1, 2^(l+1) - 1), one value
+        // per row, row-major [row][lane].  Integer: rows [2^l, 2^(l+1)), two
+        // consecutive rows per 32-bit word ([row / 2][lane], low half first),
+        // so levels >= 1 are processed as int16 pairs; the top level M - 1 is
+        // not stored but recomputed from the channel where level M - 2 needs it.
+        S buf[(FLOAT ? N : N / 2) * WAVE];
+        S ch[G * CHS];          // channel LLRs of the wave's frames
         alignas(16) Key key[2 * WAVE];
         int sel[WAVE];
         V cpm[WAVE];
@@ -122,7 +163,7 @@ template <int M, int L, bool FLOAT> struct Scl {
         const S* par;
         int stride;
         if (LEV + 1 == M) {
-            par = sm.ch + (lane / L) * N;
+            par = sm.ch + (lane / L) * CHS;
             stride = 1;
         } else {
             const int owner = gbase + (int)((ptrs >> (8 * (LEV + 1))) & 0xFF);
@@ -148,13 +189,132 @@ template <int M, int L, bool FLOAT> struct Scl {
         return o;
     }
 
+    // Integer form of level(): values two at a time as int16 pairs (v_pk_*
+    // integer ops), exact because every value and partial sum stays within
+    // +-127 * 2^m <= 32512.  Same results as level() value for value.
+    template <int LEV>
+    __device__ static V level_pk(Smem& sm, int lane, int gbase, int i, bool use_g, bool sums, uint64_t ptrs,
+                                 const uint32_t (&ub)[NW], V& d0, V& d1)
+    {
+        constexpr int n = 1 << LEV;
+        constexpr int PW = (n + 31) / 32;
+        uint32_t ps[PW];
+        if (use_g) {
+            const int st = i - n;
+            if (n < 32) {
+                ps[0] = (ub[st >> 5] >> (st & 31)) & ((1u << (n & 31)) - 1u);
+            } else {
+#pragma unroll
+                for (int w = 0; w < PW; ++w) ps[w] = ub[(st >> 5) + w];
+            }
+            polar_bits(ps, LEV);
+        }
+        uint32_t* bw = reinterpret_cast<uint32_t*>(sm.buf);
+        const uint32_t* cw = reinterpret_cast<const uint32_t*>(sm.ch + (lane / L) * CHS);
+        if constexpr (LEV + 1 == M) {
+            // The top level is recomputed where needed (top_pair), never
+            // stored; only a repetition / rate-0 node spanning it needs its sums.
+            d0 = d1 = 0;
+            if (sums) {
+                uint32_t s0 = 0, s1 = 0;
+                for (int k = 0; k < n; k += 2) {
+                    const uint32_t o = use_g ? g_pk(cw[k / 2], cw[(k + n) / 2], (ps[k >> 5] >> (k & 31)) & 3u)
+                                             : f_pk(cw[k / 2], cw[(k + n) / 2]);
+                    s0 = pk_add_u16(s0, pk_max_i16(pk_sub_u16(0u, o), 0u));
+                    s1 = pk_add_u16(s1, pk_max_i16(o, 0u));
+                }
+                d0 = (V)((s0 & 0xFFFFu) + (s0 >> 16));
+                d1 = (V)((s1 & 0xFFFFu) + (s1 >> 16));
+            }
+            return 0;
+        } else if constexpr (LEV == 0) {
+            // parent rows 2, 3 in word 1; output row 1 (high half of word 0)
+            int32_t a, b;
+            if (LEV + 2 == M) {
+                const uint32_t w = top_pair(cw, 0, i, ub);
+                a = (int16_t)(w & 0xFFFFu);
+                b = (int16_t)(w >> 16);
+            } else {
+                const int owner = gbase + (int)((ptrs >> 8) & 0xFF);
+                const uint32_t w = bw[1 * WAVE + owner];
+                a = (int16_t)(w & 0xFFFFu);
+                b = (int16_t)(w >> 16);
+            }
+            const int32_t o = use_g ? ((ps[0] & 1u) ? b - a : b + a) : f_minsum(a, b);
+            reinterpret_cast<int16_t*>(bw + lane)[1] = (int16_t)o;
+            d0 = o < 0 ? -o : 0;
+            d1 = o > 0 ? o : 0;
+            return o;
+        } else {
+            const int owner = gbase + (int)((ptrs >> (8 * (LEV + 1))) & 0xFF);
+            const uint32_t* pa = bw + n * WAVE + owner;  // parent rows 2n .. 4n-1: words n .. 2n-1
+            uint32_t vt[TW];
+            if (LEV + 2 == M) top_bits(vt, i, ub);
+            uint32_t* out = bw + (n / 2) * WAVE + lane;  // rows n .. 2n-1: words n/2 .. n-1
+            uint32_t s0 = 0, s1 = 0;
+            uint32_t o = 0;
+#pragma unroll 8
+            for (int k = 0; k < n; k += 2) {
+                uint32_t a, b;
+                if (LEV + 2 == M) {
+                    a = top_pair_v(cw, k, i, vt);
+                    b = top_pair_v(cw, k + n, i, vt);
+                } else {
+                    a = pa[(k / 2) * WAVE];
+                    b = pa[((k + n) / 2) * WAVE];
+                }
+                o = use_g ? g_pk(a, b, (ps[k >> 5] >> (k & 31)) & 3u) : f_pk(a, b);
+                out[(k / 2) * WAVE] = o;
+                if (sums) {
+                    s0 = pk_add_u16(s0, pk_max_i16(pk_sub_u16(0u, o), 0u));
+                    s1 = pk_add_u16(s1, pk_max_i16(o, 0u));
+                }
+            }
+            d0 = (V)((s0 & 0xFFFFu) + (s0 >> 16));
+            d1 = (V)((s1 & 0xFFFFu) + (s1 >> 16));
+            return (V)(int16_t)(o >> 16);  // the last value (row 2n - 1)
+        }
+    }
+
+    // The top level (M - 1) of the current path for leaf range [i, ...):
+    // f of the channel halves while i < N/2, else g with the re-encoded
+    // first-half decisions u[0, N/2) (shared by every path descending from
+    // the one that computed it, so this path's own bits give the same values).
+    static constexpr int TW = (N / 2 + 31) / 32;
+    __device__ static void top_bits(uint32_t (&vt)[TW], int i, const uint32_t (&ub)[NW])
+    {
+        if (i < N / 2) return;
+        if (N / 2 < 32) {
+            vt[0] = ub[0] & ((1u << ((N / 2) & 31)) - 1u);
+        } else {
+#pragma unroll
+            for (int w = 0; w < TW; ++w) vt[w] = ub[w];
+        }
+        polar_bits(vt, M - 1);
+    }
+    __device__ static uint32_t top_pair_v(const uint32_t* cw, int k, int i, const uint32_t (&vt)[TW])
+    {
+        const uint32_t a = cw[k / 2], b = cw[(k + N / 2) / 2];
+        return i < N / 2 ? f_pk(a, b) : g_pk(a, b, (vt[k >> 5] >> (k & 31)) & 3u);
+    }
+    __device__ static uint32_t top_pair(const uint32_t* cw, int k, int i, const uint32_t (&ub)[NW])
+    {
+        uint32_t vt[TW];
+        top_bits(vt, i, ub);
+        return top_pair_v(cw, k, i, vt);
+    }
+
     // Levels D, D-1, ..., stop for the node starting at leaf i: level D is a
     // right child (g) unless i = 0; the levels below are left children (f).
     template <int D>
     __device__ static V run(Smem& sm, int lane, int gbase, int i, int stop, int slot, uint64_t& ptrs,
                             const uint32_t (&ub)[NW], bool first, V& d0, V& d1)
     {
-        V lam = level<D>(sm, lane, gbase, i, first && i > 0, D == stop, ptrs, ub, d0, d1);
+        V lam;
+        if constexpr (FLOAT)
+            lam = level<D>(sm, lane, gbase, i, first && i > 0, D == stop, ptrs, ub, d0, d1);
+        else
+            lam = level_pk<D>(sm, lane, gbase, i, first && i > 0, D == stop, ptrs, ub, d0, d1);
         ptrs = (ptrs & ~(0xFFull << (8 * D))) | ((uint64_t)slot << (8 * D));
         __builtin_amdgcn_wave_barrier();
         if constexpr (D > 0) {
@@ -216,7 +376,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     // stage the channel values of the wave's frames (coalesced)
     for (int e = lane; e < G * N; e += WAVE) {
         const int64_t fr = (int64_t)blockIdx.x * G + e / N;
-        sm.ch[e] = (S)(fr < F ? A::load_ch(llr, fr * N + e % N) : (V)0);
+        sm.ch[(e / N) * K::CHS + e % N] = (S)(fr < F ? A::load_ch(llr, fr * N + e % N) : (V)0);
     }
     __syncthreads();
 
