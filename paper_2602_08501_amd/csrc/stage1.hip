@@ -117,6 +117,7 @@ template <int M, int L, bool FLOAT> struct Scl {
     using S = typename A::S;
     static constexpr int N = 1 << M;
     static constexpr int NW = N / 32;    // words of decided bits per path
+    static constexpr int TW = (N / 2 + 31) / 32;  // words of the first-half bits
     static constexpr int G = WAVE / L;   // frames per wave
     // channel row stride: an odd number of 32-bit words, so the G frames'
     // rows start in different LDS banks
@@ -248,39 +249,80 @@ template <int M, int L, bool FLOAT> struct Scl {
         } else {
             const int owner = gbase + (int)((ptrs >> (8 * (LEV + 1))) & 0xFF);
             const uint32_t* pa = bw + n * WAVE + owner;  // parent rows 2n .. 4n-1: words n .. 2n-1
+            uint32_t* out = bw + (n / 2) * WAVE + lane;  // rows n .. 2n-1: words n/2 .. n-1
             uint32_t vt[TW];
             if (LEV + 2 == M) top_bits(vt, i, ub);
-            uint32_t* out = bw + (n / 2) * WAVE + lane;  // rows n .. 2n-1: words n/2 .. n-1
-            uint32_t s0 = 0, s1 = 0;
-            uint32_t o = 0;
+            const bool topg = LEV + 2 == M && i >= N / 2;
+            // the uniform choices are taken once, outside the value loop
+            uint32_t r;
+            if (use_g) {
+                if (topg) r = pairs<LEV, true, true>(pa, cw, vt, ps, out, sums, d0, d1);
+                else r = pairs<LEV, true, false>(pa, cw, vt, ps, out, sums, d0, d1);
+            } else {
+                if (topg) r = pairs<LEV, false, true>(pa, cw, vt, ps, out, sums, d0, d1);
+                else r = pairs<LEV, false, false>(pa, cw, vt, ps, out, sums, d0, d1);
+            }
+            return (V)(int16_t)(r >> 16);  // the last value (row 2n - 1)
+        }
+    }
+
+    // Values of level LEV two at a time.  USEG: g (else f); TOPG: the parent
+    // is the top level in its g form (recomputed from the channel).
+    template <int LEV, bool USEG, bool TOPG, int PW>
+    __device__ static uint32_t pairs(const uint32_t* pa, const uint32_t* cw, const uint32_t (&vt)[TW],
+                                     const uint32_t (&ps)[PW], uint32_t* out, bool sums, V& d0, V& d1)
+    {
+        constexpr int n = 1 << LEV;
+        uint32_t s0 = 0, s1 = 0, o = 0;
+        if (sums) {
 #pragma unroll 8
             for (int k = 0; k < n; k += 2) {
-                uint32_t a, b;
-                if (LEV + 2 == M) {
-                    a = top_pair_v(cw, k, i, vt);
-                    b = top_pair_v(cw, k + n, i, vt);
-                } else {
-                    a = pa[(k / 2) * WAVE];
-                    b = pa[((k + n) / 2) * WAVE];
-                }
-                o = use_g ? g_pk(a, b, (ps[k >> 5] >> (k & 31)) & 3u) : f_pk(a, b);
+                o = pair_value<LEV, USEG, TOPG>(pa, cw, vt, ps, k);
                 out[(k / 2) * WAVE] = o;
-                if (sums) {
-                    s0 = pk_add_u16(s0, pk_max_i16(pk_sub_u16(0u, o), 0u));
-                    s1 = pk_add_u16(s1, pk_max_i16(o, 0u));
-                }
+                s0 = pk_add_u16(s0, pk_max_i16(pk_sub_u16(0u, o), 0u));
+                s1 = pk_add_u16(s1, pk_max_i16(o, 0u));
             }
-            d0 = (V)((s0 & 0xFFFFu) + (s0 >> 16));
-            d1 = (V)((s1 & 0xFFFFu) + (s1 >> 16));
-            return (V)(int16_t)(o >> 16);  // the last value (row 2n - 1)
+        } else {
+#pragma unroll 8
+            for (int k = 0; k < n; k += 2) {
+                o = pair_value<LEV, USEG, TOPG>(pa, cw, vt, ps, k);
+                out[(k / 2) * WAVE] = o;
+            }
         }
+        d0 = (V)((s0 & 0xFFFFu) + (s0 >> 16));
+        d1 = (V)((s1 & 0xFFFFu) + (s1 >> 16));
+        return o;
+    }
+
+    template <int LEV, bool USEG, bool TOPG, int PW>
+    __device__ static uint32_t pair_value(const uint32_t* pa, const uint32_t* cw, const uint32_t (&vt)[TW],
+                                          const uint32_t (&ps)[PW], int k)
+    {
+        constexpr int n = 1 << LEV;
+        uint32_t a, b;
+        if constexpr (LEV + 2 == M) {
+            a = top_pair_t<TOPG>(cw, k, vt);
+            b = top_pair_t<TOPG>(cw, k + n, vt);
+        } else {
+            a = pa[(k / 2) * WAVE];
+            b = pa[((k + n) / 2) * WAVE];
+        }
+        if constexpr (USEG) return g_pk(a, b, (ps[k >> 5] >> (k & 31)) & 3u);
+        else return f_pk(a, b);
+    }
+
+    template <bool TOPG>
+    __device__ static uint32_t top_pair_t(const uint32_t* cw, int k, const uint32_t (&vt)[TW])
+    {
+        const uint32_t a = cw[k / 2], b = cw[(k + N / 2) / 2];
+        if constexpr (TOPG) return g_pk(a, b, (vt[k >> 5] >> (k & 31)) & 3u);
+        else return f_pk(a, b);
     }
 
     // The top level (M - 1) of the current path for leaf range [i, ...):
     // f of the channel halves while i < N/2, else g with the re-encoded
     // first-half decisions u[0, N/2) (shared by every path descending from
     // the one that computed it, so this path's own bits give the same values).
-    static constexpr int TW = (N / 2 + 31) / 32;
     __device__ static void top_bits(uint32_t (&vt)[TW], int i, const uint32_t (&ub)[NW])
     {
         if (i < N / 2) return;
