@@ -111,6 +111,30 @@ struct Sched {
 };
 constexpr int KIND_R0 = 1, KIND_REP = 2;
 
+// Value of lane `lane ^ X` (X < 32): DPP quad permutes for X = 1, 2, else a
+// bit-mask swizzle (no memory access).
+template <int X>
+__device__ inline uint32_t xor_lane(uint32_t v)
+{
+    if constexpr (X == 1)
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    else if constexpr (X == 2)
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    else
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));
+}
+template <int X> __device__ inline uint32_t xor_key(uint32_t v) { return xor_lane<X>(v); }
+template <int X> __device__ inline uint64_t xor_key(uint64_t v)
+{
+    return ((uint64_t)xor_lane<X>((uint32_t)(v >> 32)) << 32) | xor_lane<X>((uint32_t)v);
+}
+__device__ inline uint32_t shfl_key(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
+__device__ inline uint64_t shfl_u64(uint64_t v, int src)
+{
+    return ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src) << 32) | (uint32_t)__shfl((int)(uint32_t)v, src);
+}
+__device__ inline uint64_t shfl_key(uint64_t v, int src) { return shfl_u64(v, src); }
+
 template <int M, int L, bool FLOAT> struct Scl {
     using A = Arith<FLOAT>;
     using V = typename A::V;
@@ -119,9 +143,7 @@ template <int M, int L, bool FLOAT> struct Scl {
     static constexpr int NW = N / 32;    // words of decided bits per path
     static constexpr int TW = (N / 2 + 31) / 32;  // words of the first-half bits
     static constexpr int G = WAVE / L;   // frames per wave
-    // channel row stride: an odd number of 32-bit words, so the G frames'
-    // rows start in different LDS banks
-    static constexpr int CHS = N + (sizeof(S) == 2 ? 2 : 1);
+    static constexpr int CHS = N;  // channel row stride
     using Key = typename std::conditional<FLOAT, uint64_t, uint32_t>::type;
 
     struct Smem {
@@ -132,12 +154,6 @@ template <int M, int L, bool FLOAT> struct Scl {
         // not stored but recomputed from the channel where level M - 2 needs it.
         S buf[(FLOAT ? N : N / 2) * WAVE];
         S ch[G * CHS];          // channel LLRs of the wave's frames
-        alignas(16) Key key[2 * WAVE];
-        int sel[WAVE];
-        V cpm[WAVE];
-        int cvalid[WAVE];
-        uint64_t ptr[WAVE];
-        uint32_t ub[NW * WAVE];
     };
 
     // Recompute level LEV of this lane's path from level LEV + 1 (the
@@ -391,6 +407,44 @@ template <int M, int L, bool FLOAT> struct Scl {
             return ((valid ? (uint32_t)pm : 0x7FFFFFu) << 7) | (uint32_t)idx;
         }
     }
+    __device__ static int key_index(Key k) { return (int)(k & (FLOAT ? 0xFFu : 0x7Fu)); }
+    __device__ static bool key_valid(Key k)
+    {
+        if constexpr (FLOAT) return (uint32_t)(k >> 8) != 0xFFFFFFFFu;
+        else return (k >> 7) != 0x7FFFFFu;
+    }
+    __device__ static V key_pm(Key k)
+    {
+        if constexpr (FLOAT) return __uint_as_float((uint32_t)(k >> 8));
+        else return (V)(k >> 7);
+    }
+
+    // Bitonic sort, ascending, of the 2L keys of a frame: lane slot s holds
+    // elements 2s (x0) and 2s + 1 (x1).  Stages of size KS = 2, 4, ..., 2L.
+    template <int KS>
+    __device__ static void bitonic(Key& x0, Key& x1, int s)
+    {
+        if constexpr (KS <= 2 * L) {
+            stage<KS, KS / 2>(x0, x1, s);
+            bitonic<KS * 2>(x0, x1, s);
+        }
+    }
+    template <int KS, int J>
+    __device__ static void stage(Key& x0, Key& x1, int s)
+    {
+        const bool up = ((2 * s) & KS) == 0;
+        if constexpr (J == 1) {
+            const Key lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
+            x0 = up ? lo : hi;
+            x1 = up ? hi : lo;
+        } else {
+            const Key y0 = xor_key<J / 2>(x0), y1 = xor_key<J / 2>(x1);
+            const bool keep_min = (((2 * s) & J) == 0) == up;
+            x0 = keep_min ? (y0 < x0 ? y0 : x0) : (y0 < x0 ? x0 : y0);
+            x1 = keep_min ? (y1 < x1 ? y1 : x1) : (y1 < x1 ? x1 : y1);
+            stage<KS, J / 2>(x0, x1, s);
+        }
+    }
 };
 
 template <int M, int L, bool FLOAT>
@@ -447,66 +501,31 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
             if (valid) pm = pm + d0;
             continue;  // u = 0 already
         }
-        // information bit: rank the 2L children by (PM, parent slot, bit)
-        V cp[2];
-        cp[0] = (V)(pm + d0);
-        cp[1] = (V)(pm + d1);
-        Key key[2];
-        key[0] = K::make_key(valid, cp[0], 2 * slot);
-        key[1] = K::make_key(valid, cp[1], 2 * slot + 1);
-        sm.key[2 * lane] = key[0];
-        sm.key[2 * lane + 1] = key[1];
-        sm.ptr[lane] = ptrs;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) sm.ub[w * WAVE + lane] = ub[w];
-        __syncthreads();
-        int rank0 = 0, rank1 = 0;
-        if constexpr (!FLOAT && L >= 2) {
-            const uint4* kv = (const uint4*)&sm.key[2 * gbase];
-#pragma unroll
-            for (int c = 0; c < 2 * L / 4; ++c) {
-                const uint4 o = kv[c];
-                rank0 += (o.x < key[0]) + (o.y < key[0]) + (o.z < key[0]) + (o.w < key[0]);
-                rank1 += (o.x < key[1]) + (o.y < key[1]) + (o.z < key[1]) + (o.w < key[1]);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 2 * L; ++c) {
-                const Key o = sm.key[2 * gbase + c];
-                rank0 += o < key[0];
-                rank1 += o < key[1];
-            }
-        }
-        if (rank0 < L) {
-            sm.sel[gbase + rank0] = 2 * slot;
-            sm.cpm[gbase + rank0] = cp[0];
-            sm.cvalid[gbase + rank0] = valid ? 1 : 0;
-        }
-        if (rank1 < L) {
-            sm.sel[gbase + rank1] = 2 * slot + 1;
-            sm.cpm[gbase + rank1] = cp[1];
-            sm.cvalid[gbase + rank1] = valid ? 1 : 0;
-        }
-        __syncthreads();
-        const int c = sm.sel[lane];
+        // information bit: the 2L children sorted by (PM, parent slot, bit)
+        // with a bitonic network over the frame's L lanes (two keys per lane,
+        // partners reached through DPP / swizzles); slot s takes the s-th key,
+        // which also names its parent slot and bit
+        Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
+        Key x1 = K::make_key(valid, (V)(pm + d1), 2 * slot + 1);
+        K::template bitonic<2>(x0, x1, slot);
+        const int src = gbase + (slot >> 1);
+        const Key y0 = shfl_key(x0, src), y1 = shfl_key(x1, src);
+        const Key mine = (slot & 1) ? y1 : y0;
+        const int c = K::key_index(mine);
+        valid = K::key_valid(mine);
+        pm = K::key_pm(mine);
         const int par = gbase + (c >> 1);
-        pm = sm.cpm[lane];
-        valid = sm.cvalid[lane] != 0;
-        ptrs = sm.ptr[par];
+        ptrs = shfl_u64(ptrs, par);
 #pragma unroll
-        for (int w = 0; w < NW; ++w) ub[w] = sm.ub[w * WAVE + par];
+        for (int w = 0; w < NW; ++w) ub[w] = (uint32_t)__shfl((int)ub[w], par);
         ub[last >> 5] |= (uint32_t)(c & 1) << (last & 31);
-        __syncthreads();
     }
 
     // final order: (PM, slot) ascending
     const uint64_t fkey = ((uint64_t)(valid ? A::key_bits(pm) : 0xFFFFFFFFu) << 8) | (uint64_t)slot;
-    uint64_t* fk = (uint64_t*)sm.ptr;
-    fk[lane] = fkey;
-    __syncthreads();
     int rank = 0;
 #pragma unroll
-    for (int c = 0; c < L; ++c) rank += fk[gbase + c] < fkey;
+    for (int c = 0; c < L; ++c) rank += shfl_u64(fkey, gbase + c) < fkey;
     uint32_t cw[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) cw[w] = ub[w];
