@@ -102,9 +102,13 @@ int device_cus()
 // Failing frames are appended to the compacted list with one atomic per
 // workgroup (their order in the list is irrelevant: every frame is decoded
 // independently and results are written per frame).
-__global__ void hdr_zero_kernel(int32_t* __restrict__ hdr, int n)
+// Clears a segment header (and, for the first segment of a call, the
+// caller's statistics) before the compaction.
+__global__ void hdr_zero_kernel(int32_t* __restrict__ hdr, int n, int32_t* __restrict__ stats, int ns)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) hdr[i] = 0;
+    if (stats)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x) stats[i] = 0;
 }
 
 __global__ __launch_bounds__(256) void compact_kernel(const uint8_t* __restrict__ crc_ok, int64_t F,
@@ -141,7 +145,9 @@ __global__ void stats_zero_kernel(int32_t* stats, int n)
     for (int i = threadIdx.x; i < n; i += blockDim.x) stats[i] = 0;
 }
 
-__global__ void stats_add_kernel(const int32_t* __restrict__ hdr, int T, int32_t* __restrict__ stats)
+// Per-iteration active counts and the out-of-table count into stats
+// (workgroup 0 of the final choice, when every count is final).
+__device__ inline void stats_add(const int32_t* __restrict__ hdr, int T, int32_t* __restrict__ stats)
 {
     const int t = threadIdx.x;
     if (t < T) atomicAdd(&stats[1 + t], hdr[2 + t]);
@@ -149,74 +155,54 @@ __global__ void stats_add_kernel(const int32_t* __restrict__ hdr, int T, int32_t
 }
 
 // ---------------------------------------------------------------- init
-// Thread per (frame, path, 16 positions).  Decided frames take their first
-// anchor; the paths of failing frames become columns: centre bits, z and the
-// metric M(c) = sum_{c_j = 1} q_j (int8 form).  Thread 0 also publishes the
-// number of columns for the first search.
+// Two index ranges, PP = KP/16 threads (16 positions each) per item:
+//   frames f < F: every frame's move log is filled with -1, and a decided
+//     frame takes its first anchor (decision, k = 0, metric);
+//   columns c < hdr[0] L of the failing frames (c = list index * L + path):
+//     centre bits, -z and the metric M(c) = sum_{c_j = 1} q_j (int8 form).
+// Thread 0 also publishes the number of columns for the first search.
 template <bool FLOAT>
 __global__ __launch_bounds__(256) void init_kernel(
     const void* __restrict__ llr, const uint8_t* __restrict__ anchors, int64_t F, int L, int T, int N, int KP,
-    int32_t* __restrict__ hdr, const int32_t* __restrict__ slot, int32_t* __restrict__ act0,
-    uint64_t* __restrict__ key64, int32_t* __restrict__ metric, uint8_t* __restrict__ cw,
-    void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
+    int32_t* __restrict__ hdr, const int32_t* __restrict__ slot, const int32_t* __restrict__ fid,
+    int32_t* __restrict__ act0, uint64_t* __restrict__ key64, int32_t* __restrict__ metric,
+    uint8_t* __restrict__ cw, void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
     int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves, int32_t* __restrict__ stats)
 {
-    const int PP = KP / 16;  // pieces per path (4, 8 or 16: a path's pieces share a wave)
+    const int PP = KP / 16;  // pieces per item (4, 8 or 16: an item's pieces share a wave)
     const int NB = N / 8;
-    const int64_t total = F * L * PP;
+    const int64_t nfail = hdr[0];
+    const int64_t part1 = F * PP;
+    const int64_t total = part1 + nfail * L * PP;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        hdr[2] = hdr[0] * L;
-        if (stats) atomicAdd(&stats[0], hdr[0]);
+        hdr[2] = (int32_t)(nfail * L);
+        if (stats) atomicAdd(&stats[0], (int32_t)nfail);
     }
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ((total + 63) & ~int64_t(63));
          g += (int64_t)gridDim.x * blockDim.x) {
-        const bool live = g < total;
-        const int64_t idx = live ? g / PP : 0;
+        if (g >= total) continue;  // whole items: total and part1 are multiples of PP
         const int piece = (int)(g % PP);
         const int j0 = 16 * piece;
-        const int64_t f = idx / L;
-        const int k = (int)(idx % L);
-        const bool inpos = live && j0 < N;
-        const uint32_t bits = inpos ? *(const uint16_t*)(anchors + (size_t)idx * NB + 2 * piece) : 0u;
-        const int s = live ? slot[f] : -1;
-        int part = 0;
-        if (!FLOAT && inpos) {
-            const int8_t* q = (const int8_t*)llr + (size_t)f * N + j0;
-            v4i qv = *(const v4i*)q;
-            v4i zv;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                uint32_t wq = (uint32_t)qv[d], wz = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int v = (int8_t)(wq >> (8 * b));
-                    const int bit = (bits >> (4 * d + b)) & 1;
-                    part += bit ? v : 0;
-                    wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
-                }
-                zv[d] = (int)wz;
+        const bool inpos = j0 < N;
+        if (g < part1) {
+            // ---- frame f
+            const int64_t f = g / PP;
+            if (out_moves)
+                for (int e = piece; e < L * T; e += PP) out_moves[(size_t)f * L * T + e] = -1;
+            if (slot[f] >= 0) continue;  // failing: its columns are items of the second range
+            const uint32_t bits = inpos ? *(const uint16_t*)(anchors + (size_t)f * L * NB + 2 * piece) : 0u;
+            int part = 0;
+            if (!FLOAT && inpos) {
+                const int8_t* q = (const int8_t*)llr + (size_t)f * N + j0;
+                for (int j = 0; j < 16; ++j) part += ((bits >> j) & 1) ? q[j] : 0;
             }
-            if (s >= 0) *(v4i*)((int8_t*)zbuf + (size_t)((int64_t)s * L + k) * KP + j0) = zv;
-        } else if (!FLOAT && live && s >= 0) {
-            *(v4i*)((int8_t*)zbuf + (size_t)((int64_t)s * L + k) * KP + j0) = v4i{0, 0, 0, 0};
-        }
-        if (FLOAT && inpos && s >= 0) {
-            const float* y = (const float*)llr + (size_t)f * N + j0;
-            float* z = (float*)zbuf + (size_t)((int64_t)s * L + k) * N + j0;
-#pragma unroll
-            for (int j = 0; j < 16; ++j) z[j] = ((bits >> j) & 1) ? -y[j] : y[j];
-        }
-        // sum the pieces of this path (consecutive lanes)
-        for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
-        if (!live) continue;
-        if (s < 0) {
-            if (k != 0) goto moves_fill;
+            for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
             if (inpos) *(uint16_t*)(out_cw + (size_t)f * NB + 2 * piece) = (uint16_t)bits;
             if (piece == 0) {
                 if (out_k) out_k[f] = 0;
                 if (out_metric) {
                     if (FLOAT) {
-                        const uint8_t* a = anchors + (size_t)idx * NB;
+                        const uint8_t* a = anchors + (size_t)f * L * NB;
                         const float* y = (const float*)llr + (size_t)f * N;
                         float e = 0.0f;
                         for (int j = 0; j < N; ++j) {
@@ -231,7 +217,38 @@ __global__ __launch_bounds__(256) void init_kernel(
                 }
             }
         } else {
-            const int64_t col = (int64_t)s * L + k;
+            // ---- column c of the failing frames
+            const int64_t col = (g - part1) / PP;
+            const int64_t s = col / L;
+            const int k = (int)(col % L);
+            const int64_t f = fid[s];
+            const uint32_t bits = inpos ? *(const uint16_t*)(anchors + ((size_t)f * L + k) * NB + 2 * piece) : 0u;
+            int part = 0;
+            if (!FLOAT) {
+                v4i zv = v4i{0, 0, 0, 0};
+                if (inpos) {
+                    const v4i qv = *(const v4i*)((const int8_t*)llr + (size_t)f * N + j0);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        uint32_t wq = (uint32_t)qv[d], wz = 0;
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            const int v = (int8_t)(wq >> (8 * b));
+                            const int bit = (bits >> (4 * d + b)) & 1;
+                            part += bit ? v : 0;
+                            wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
+                        }
+                        zv[d] = (int)wz;
+                    }
+                }
+                *(v4i*)((int8_t*)zbuf + (size_t)col * KP + j0) = zv;
+            } else if (inpos) {
+                const float* y = (const float*)llr + (size_t)f * N + j0;
+                float* z = (float*)zbuf + (size_t)col * N + j0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) z[j] = ((bits >> j) & 1) ? -y[j] : y[j];
+            }
+            for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
             if (inpos) *(uint16_t*)(cw + (size_t)col * NB + 2 * piece) = (uint16_t)bits;
             if (piece == 0) {
                 act0[col] = (int32_t)col;
@@ -239,9 +256,6 @@ __global__ __launch_bounds__(256) void init_kernel(
                 if (!FLOAT) metric[col] = part;
             }
         }
-    moves_fill:
-        if (out_moves)
-            for (int t = piece; t < T; t += PP) out_moves[(size_t)idx * T + t] = -1;
     }
 }
 
@@ -678,8 +692,9 @@ template <bool FLOAT>
 __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __restrict__ hdr,
                               const int32_t* __restrict__ fid, int L, int N, const int32_t* __restrict__ metric,
                               const uint8_t* __restrict__ cw, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
-                              int32_t* __restrict__ out_metric)
+                              int32_t* __restrict__ out_metric, int T, int32_t* __restrict__ stats)
 {
+    if (stats && blockIdx.x == 0) stats_add(hdr, T, stats);
     const int f2 = hdr[0];
     const int NB = N / 8;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < f2; s += gridDim.x * blockDim.x) {
@@ -790,22 +805,25 @@ void launch_search_multi(const MultiSearch& ms, int maxN, int variant, int block
 }
 
 // Phases of stage 2 for one segment.
-void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipStream_t s)
+// zero_stats: this is the first segment of the call, whose first kernel also
+// clears the caller's statistics.
+void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, bool zero_stats,
+                  hipStream_t s)
 {
     const int N = 1 << sg.m, KP = kpad(N);
     const bool fl = sg.dtype == MPWSD_F32;
-    hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(64), 0, s, w.hdr, 4 + T);
+    hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(128), 0, s, w.hdr, 4 + T, zero_stats ? stats : nullptr, 2 + T);
     hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((sg.F + 255) / 256)), dim3(256), 0, s, sg.crc_ok, sg.F, w.hdr,
                        w.fid, w.slot);
-    const int64_t work = sg.F * L * (KP / 16);
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 65536));
+    const int64_t work = sg.F * (int64_t)(L + 1) * (KP / 16);  // upper bound on the items' threads
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 8 * device_cus()));
     if (fl)
         hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
-                           w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
                            sg.out_metric, sg.out_moves, stats);
     else
         hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
-                           w.hdr, w.slot, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
                            sg.out_metric, sg.out_moves, stats);
 }
 
@@ -829,18 +847,17 @@ void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
     if (sg.dtype == MPWSD_F32)
         hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N, w.metric,
-                           w.cw, sg.out_cw, sg.out_k, sg.out_metric);
+                           w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats);
     else
         hipLaunchKernelGGL(select_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
-                           w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric);
-    if (stats) hipLaunchKernelGGL(stats_add_kernel, dim3(1), dim3(128), 0, s, w.hdr, T, stats);
+                           w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats);
 }
 
-int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipEvent_t* ev,
-                int variant, int blocks_per_cu, hipStream_t s)
+int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, bool zero_stats,
+                hipEvent_t* ev, int variant, int blocks_per_cu, hipStream_t s)
 {
     const int N = 1 << sg.m;
-    seg_prologue(sg, L, T, w, stats, s);
+    seg_prologue(sg, L, T, w, stats, zero_stats, s);
     for (int t = 0; t < T; ++t) {
         if (ev) (void)hipEventRecord(ev[2 * t], s);
         if (sg.dtype == MPWSD_F32)
@@ -865,7 +882,7 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
     int maxN = 0;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
-        seg_prologue(segs[i], L, T, w[i], stats, s);
+        seg_prologue(segs[i], L, T, w[i], stats, base.nseg == 0, s);
         SegSearch& g = base.s[base.nseg++];
         g.z = (const int8_t*)w[i].z;
         g.moves = segs[i].moves;
@@ -971,7 +988,11 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
         return mpwsd::fail(MPWSD_ERR_SIZE, "mpwsd_decode_batch: workspace needs %zu bytes, got %zu", need, ws_bytes);
     if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
         return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: workspace must be 256-byte aligned");
-    if (stats) hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, stream, stats, 2 + T);
+    // the first non-empty segment's first kernel clears stats; with none, a
+    // kernel of its own does
+    bool any = false;
+    for (int i = 0; i < nseg; ++i) any = any || segs[i].F > 0;
+    if (stats && !any) hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, stream, stats, 2 + T);
     uint8_t* base = (uint8_t*)ws;
     std::vector<SegWs> w(nseg);
     for (int i = 0; i < nseg; ++i) {
@@ -981,10 +1002,12 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
     if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8)
         return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr, variant,
                          bpc, stream);
+    bool first = true;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
         hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
-        rc = run_segment(segs[i], L, T, w[i], stats, ev, variant, bpc, stream);
+        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant, bpc, stream);
+        first = false;
         if (rc != MPWSD_OK) return rc;
     }
     return MPWSD_OK;
