@@ -500,9 +500,19 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
 }
 
 // ---------------------------------------------------------------- int8 resolve
-// Thread per active column: the search left the exact (S_min, p*) in the key;
-// apply the move when S_min < 0 (flip the centre bits and the signs of the
-// stored -z on the move's support, update M, log p*) and append the column
+// Negate the int8 lanes of x whose bit is set in the low 4 bits of nib
+// (two's complement per byte, no carry between bytes).
+__device__ inline uint32_t neg_bytes(uint32_t x, uint32_t nib)
+{
+    const uint32_t one = ((nib & 15u) * 0x00204081u) & 0x01010101u;  // bit b -> byte b
+    const uint32_t t = x ^ (one * 0xFFu);
+    return ((t & 0x7F7F7F7Fu) + one) ^ (t & 0x80808080u);
+}
+
+// Thread per active column: the search left the exact (S_min, p*) in the
+// key; when S_min < 0 the move is applied (centre bits flip, the stored -z
+// changes sign on the move's support, M += S, p* logged), the -z column being
+// read and written in independent 16-byte pieces, and the column is appended
 // to the next active list with one atomic per wave.
 __global__ __launch_bounds__(256) void resolve_i8_kernel(
     int8_t* __restrict__ z, uint8_t* __restrict__ cw, int32_t* __restrict__ metric, const uint8_t* __restrict__ moves,
@@ -512,7 +522,7 @@ __global__ __launch_bounds__(256) void resolve_i8_kernel(
 {
     const int lane = threadIdx.x & 63;
     const int n = hdr[2 + t];
-    const int NB = N / 8, NWD = N / 32;
+    const int NB = N / 8;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
         const int pos = base + lane;
@@ -528,16 +538,24 @@ __global__ __launch_bounds__(256) void resolve_i8_kernel(
                 if (p >= P) {
                     atomicAdd(&hdr[1], 1);
                 } else {
-                    const uint32_t* mv = (const uint32_t*)(moves + (size_t)p * NB);
-                    uint32_t* c32 = (uint32_t*)(cw + (size_t)col * NB);
-                    int8_t* zc = z + (size_t)col * KP;
-                    for (int wd = 0; wd < NWD; ++wd) {
-                        uint32_t bits = mv[wd];
-                        c32[wd] ^= bits;
-                        while (bits) {
-                            const int j = 32 * wd + __builtin_ctz(bits);
-                            zc[j] = (int8_t)(-zc[j]);
-                            bits &= bits - 1;
+                    const uint16_t* mv = (const uint16_t*)(moves + (size_t)p * NB);
+                    uint16_t* c16 = (uint16_t*)(cw + (size_t)col * NB);
+                    v4i* zp = (v4i*)(z + (size_t)col * KP);
+                    for (int g = 0; g < N / 16; g += 4) {  // 64 positions at a time
+                        uint32_t bits[4];
+                        v4i zv[4];
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            bits[h] = g + h < N / 16 ? mv[g + h] : 0u;
+                            if (g + h < N / 16) zv[h] = zp[g + h];
+                        }
+#pragma unroll
+                        for (int h = 0; h < 4; ++h) {
+                            if (g + h >= N / 16) continue;
+                            c16[g + h] = (uint16_t)(c16[g + h] ^ bits[h]);
+#pragma unroll
+                            for (int d = 0; d < 4; ++d) zv[h][d] = (int)neg_bytes((uint32_t)zv[h][d], bits[h] >> (4 * d));
+                            zp[g + h] = zv[h];
                         }
                     }
                     metric[col] += S;
