@@ -283,7 +283,9 @@ def main():
         "complexity_ed_units": ed_units if nseg > 1 else ed_units[0],
         "wall_s": wall,
         "ms_per_step_eager": ms_eager,
-        "search_tiles": {"variant": variant, "blocks_per_cu": bpc, **_lib.mpwsd_search_variants()[variant]},
+        "search_tiles": [{"iteration": t, "variant": v, "blocks_per_cu": b,
+                          **{k: x for k, x in _lib.mpwsd_search_variants()[v].items() if k != "blocks_per_cu"}}
+                         for t, (v, b) in enumerate(zip(variant, bpc))],
     }
     if args.cpu_frames < 0:
         args.cpu_frames = {"rm38": 4096, "rm26s2": 8192, "rm27osd": 16384}.get(args.workload, F_total)

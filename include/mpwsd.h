@@ -260,6 +260,11 @@ typedef struct mpwsd_options {
                             stream, for timing with hipEventElapsedTime; when
                             several int8 segments share one search launch,
                             only events[2 t] and events[2 t + 1] are recorded */
+    const int* iter_variant;        /* NULL, or T host entries: the tile variant of
+                                       iteration t's search (-1: library default);
+                                       overrides search_variant */
+    const int* iter_blocks_per_cu;  /* NULL, or T host entries overriding
+                                       blocks_per_cu per iteration */
 } mpwsd_options;
 
 /*

@@ -35,7 +35,8 @@ class VariantInfo(ctypes.Structure):
 
 class Options(ctypes.Structure):
     """struct mpwsd_options."""
-    _fields_ = [("search_variant", _i), ("blocks_per_cu", _i), ("events", ctypes.POINTER(_p))]
+    _fields_ = [("search_variant", _i), ("blocks_per_cu", _i), ("events", ctypes.POINTER(_p)),
+                ("iter_variant", ctypes.POINTER(_i)), ("iter_blocks_per_cu", ctypes.POINTER(_i))]
 
 
 class ServerCode(ctypes.Structure):
@@ -165,10 +166,21 @@ def mpwsd_decode_batch(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, s
 
 
 
-def mpwsd_decode_batch_ex(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, variant: int = -1,
-                          blocks_per_cu: int = 0, event_handles=None, stream=None) -> int:
+def mpwsd_decode_batch_ex(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, variant=-1,
+                          blocks_per_cu=0, event_handles=None, stream=None) -> int:
+    """variant / blocks_per_cu: one value, or a list of T values (one per iteration)."""
     arr = segments_array(segs)
-    opt = Options(variant, blocks_per_cu, None)
+    opt = Options(-1, 0, None, None, None)
+    if isinstance(variant, (list, tuple)):
+        iv = (_i * len(variant))(*variant)
+        opt.iter_variant = ctypes.cast(iv, ctypes.POINTER(_i))
+    else:
+        opt.search_variant = variant
+    if isinstance(blocks_per_cu, (list, tuple)):
+        ib = (_i * len(blocks_per_cu))(*blocks_per_cu)
+        opt.iter_blocks_per_cu = ctypes.cast(ib, ctypes.POINTER(_i))
+    else:
+        opt.blocks_per_cu = blocks_per_cu
     if event_handles is not None:
         evs = (_p * len(event_handles))(*event_handles)
         opt.events = ctypes.cast(evs, ctypes.POINTER(_p))

@@ -3,7 +3,8 @@
 Times every search tile variant (column blocks per wave x waves per
 workgroup) and persistent-grid size on the caller's own batch, checks that
 all of them produce bit-identical decisions and move logs, and keeps the
-fastest.  Choices are cached per device, code, list size, iteration count and
+fastest for every iteration separately (the active columns shrink from
+iteration to iteration, and small searches prefer small tiles).  Choices are cached per device, code, list size, iteration count and
 batch size in a JSON file (MPWSD_TUNE_CACHE, default
 ~/.cache/mpwsd/tune.json).
 """
@@ -61,23 +62,23 @@ def candidates(N: int, multi: bool = False):
 
 
 def tune(stage2, llrs, anchors, crc_oks, reps: int = 3, stream=None, use_cache: bool = True, verbose=False):
-    """Returns (variant, blocks_per_cu) for this Stage2 and its inputs."""
+    """Returns ([variant] * T, [blocks_per_cu] * T) for this Stage2 and its inputs."""
     key = _key(stage2)
     cache = _load() if use_cache else {}
-    if key in cache:
-        return tuple(cache[key]["choice"])
+    if key in cache and isinstance(cache[key].get("choice", [None])[0], list):
+        v, b = cache[key]["choice"]
+        return list(v), list(b)
     stream = stream or torch.cuda.current_stream()
     T = stage2.T
     nseg = len(stage2.codes_F)
     multi = nseg > 1 and stage2.dt == _lib.MPWSD_I8
-    n_launch = T if multi else T * nseg
     events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * T * nseg)]
     for e in events:
         e.record(stream)
     ref = None
-    results = []
+    results = []  # (variant, bpc, [ms per iteration])
     for var, bpc in candidates(max(c.N for c, _ in stage2.codes_F), multi):
-        times = []
+        per_iter = None
         for r in range(reps + 1):
             stage2.run(llrs, anchors, crc_oks, stream=stream, events=events, variant=var, blocks_per_cu=bpc)
             stream.synchronize()
@@ -89,15 +90,23 @@ def tune(stage2, llrs, anchors, crc_oks, reps: int = 3, stream=None, use_cache: 
                     for k in ref[0]:
                         if not all(torch.equal(a[k], b[k]) for a, b in zip(ref, out)):
                             raise RuntimeError("search variant %d / %d differs from variant %d in %s"
-                                               % (var, bpc, results[0][1], k))
+                                               % (var, bpc, results[0][0], k))
                 continue
-            times.append(sum(events[2 * t].elapsed_time(events[2 * t + 1]) for t in range(n_launch)))
-        results.append((min(times), var, bpc))
+            # per iteration: the launches of every segment (one launch when several codes share it)
+            ms = [sum(events[2 * (s * T + t)].elapsed_time(events[2 * (s * T + t) + 1])
+                      for s in range(1 if multi else nseg)) for t in range(T)]
+            per_iter = ms if per_iter is None else [min(a, b) for a, b in zip(per_iter, ms)]
+        results.append((var, bpc, per_iter))
         if verbose:
-            print("variant %d blocks/CU %d: %.3f ms" % (var, bpc, min(times)))
-    best = min(results)
-    cache[key] = {"choice": [best[1], best[2]], "search_ms": best[0],
-                  "all": [[v, b, t] for t, v, b in results]}
+            print("variant %d blocks/CU %d: %s ms" % (var, bpc, " ".join("%.3f" % x for x in per_iter)))
+    best_v, best_b, best_ms = [], [], []
+    for t in range(T):
+        v, b, ms = min(results, key=lambda x: x[2][t])
+        best_v.append(v)
+        best_b.append(b)
+        best_ms.append(ms[t])
+    cache[key] = {"choice": [best_v, best_b], "search_ms": sum(best_ms),
+                  "all": [[v, b, ms] for v, b, ms in results]}
     if use_cache:
         _save(cache)
-    return best[1], best[2]
+    return best_v, best_b

@@ -872,7 +872,7 @@ void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
 }
 
 int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, bool zero_stats,
-                hipEvent_t* ev, int variant, int blocks_per_cu, hipStream_t s)
+                hipEvent_t* ev, const int* variant, const int* blocks_per_cu, hipStream_t s)
 {
     const int N = 1 << sg.m;
     seg_prologue(sg, L, T, w, stats, zero_stats, s);
@@ -882,7 +882,7 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
             launch_search_f32(w, sg, t, s, device_cus() * 4);
         else
             mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr + 2 + t,
-                                    (long long*)w.key64, variant, blocks_per_cu, s);
+                                    (long long*)w.key64, variant[t], blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         seg_resolve(sg, L, T, w, t, s);
     }
@@ -894,7 +894,7 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
 
 // Several int8 segments: every iteration's search of all codes is ONE launch.
 int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w, int32_t* stats, hipEvent_t* ev,
-              int variant, int blocks_per_cu, hipStream_t s)
+              const int* variant, const int* blocks_per_cu, hipStream_t s)
 {
     MultiSearch base{};
     int maxN = 0;
@@ -918,7 +918,7 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
             ++j;
         }
         if (ev) (void)hipEventRecord(ev[2 * t], s);
-        if (ms.nseg > 0) launch_search_multi(ms, maxN, variant, blocks_per_cu, s);
+        if (ms.nseg > 0) launch_search_multi(ms, maxN, variant[t], blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         for (int i = 0; i < nseg; ++i)
             if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, s);
@@ -995,11 +995,18 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
 {
     int rc = validate(segs, nseg, L, T, true);
     if (rc != MPWSD_OK) return rc;
-    const int variant = opt ? opt->search_variant : -1;
-    const int bpc = opt ? opt->blocks_per_cu : 0;
-    if (variant < -1 || variant >= kNumVariants)
-        return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: search_variant %d out of range", variant);
-    if (bpc < 0 || bpc > 16) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: blocks_per_cu %d", bpc);
+    // search tiles of every iteration
+    std::vector<int> variant(T, opt ? opt->search_variant : -1), bpc(T, opt ? opt->blocks_per_cu : 0);
+    for (int t = 0; t < T; ++t) {
+        if (opt && opt->iter_variant) variant[t] = opt->iter_variant[t];
+        if (opt && opt->iter_blocks_per_cu) bpc[t] = opt->iter_blocks_per_cu[t];
+        if (variant[t] < -1 || variant[t] >= kNumVariants)
+            return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: search variant %d (iteration %d) out of range",
+                               variant[t], t);
+        if (bpc[t] < 0 || bpc[t] > 16)
+            return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: blocks_per_cu %d (iteration %d) out of range",
+                               bpc[t], t);
+    }
     size_t need = 0;
     for (int i = 0; i < nseg; ++i) need += carve(segs[i], L, T, nullptr).bytes;
     if (!ws || ws_bytes < need)
@@ -1018,13 +1025,13 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
         base += w[i].bytes;
     }
     if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8)
-        return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr, variant,
-                         bpc, stream);
+        return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr,
+                         variant.data(), bpc.data(), stream);
     bool first = true;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
         hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
-        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant, bpc, stream);
+        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant.data(), bpc.data(), stream);
         first = false;
         if (rc != MPWSD_OK) return rc;
     }

@@ -143,15 +143,17 @@ class Stage2:
                                 _ptr(o.get("moves")) if o else None))
         return segs
 
-    def run(self, llrs, anchors, crc_oks, stream=None, events=None, variant: int = -1, blocks_per_cu: int = 0,
+    def run(self, llrs, anchors, crc_oks, stream=None, events=None, variant=-1, blocks_per_cu=0,
             raw_stream=None):
         """events: optional list of 2 * T * nseg recorded torch.cuda.Event
         (enable_timing=True); re-recorded around every search launch.
+        variant / blocks_per_cu: one value, or T values (per iteration).
         raw_stream: a hipStream_t handle (int) to enqueue on instead of a
         torch stream (used while recording a graph)."""
         segs = self._segs(llrs, anchors, crc_oks)
         st = raw_stream if raw_stream is not None else _stream(stream)
-        if events is None and variant < 0 and blocks_per_cu == 0:
+        per_iter = isinstance(variant, (list, tuple)) or isinstance(blocks_per_cu, (list, tuple))
+        if events is None and not per_iter and variant < 0 and blocks_per_cu == 0:
             check(_lib.mpwsd_decode_batch(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
                                           self.stats.data_ptr(), st))
         else:

@@ -155,6 +155,12 @@ def test_search_variants_and_option_errors():
     assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, variant=len(vs)) == _lib.MPWSD_ERR_ARG
     assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, variant=-2) == _lib.MPWSD_ERR_ARG
     assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None, blocks_per_cu=-1) == _lib.MPWSD_ERR_ARG
+    # per-iteration tiles: every entry is checked
+    assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None,
+                                      variant=[0, 1, 2, 0, 1, 2, 0, len(vs)]) == _lib.MPWSD_ERR_ARG
+    assert "iteration 7" in _lib.last_error()
+    assert _lib.mpwsd_decode_batch_ex([_seg()], 8, 8, 0x10000, ok, None,
+                                      blocks_per_cu=[1, 2, 3, 4, 17, 1, 1, 1]) == _lib.MPWSD_ERR_ARG
     assert _lib.load().mpwsd_graph_launch(None, None) == _lib.MPWSD_ERR_ARG
     assert _lib.load().mpwsd_graph_destroy(None) == 0
 

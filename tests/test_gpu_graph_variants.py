@@ -41,6 +41,13 @@ def test_variants_bit_identical(wl, L, T, F):
             torch.cuda.synchronize()
             for k in ref:
                 assert torch.equal(ref[k], st.outs[0][k]), (var, bpc, k)
+    # a different tile variant and grid for every iteration
+    iv = [t % nv for t in range(T)]
+    ib = [(0, 1, 2, 3)[t % 4] for t in range(T)]
+    st.run([q], [s1["anchors"]], [s1["crc_ok"]], variant=iv, blocks_per_cu=ib)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(ref[k], st.outs[0][k]), ("per iteration", k)
 
 
 def test_graph_replay_matches_eager():
