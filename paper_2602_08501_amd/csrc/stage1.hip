@@ -421,28 +421,71 @@ template <int M, int L, bool FLOAT> struct Scl {
 
     // Bitonic sort, ascending, of the 2L keys of a frame: lane slot s holds
     // elements 2s (x0) and 2s + 1 (x1).  Stages of size KS = 2, 4, ..., 2L.
+    // Stage KS/J of the network has the number base(KS) + log2(KS/2) - log2(J),
+    // base(KS) = number of stages of the smaller sizes.
+    static constexpr int lg2(int v) { return v <= 1 ? 0 : 1 + lg2(v / 2); }
+    template <int KS, int J>
+    static constexpr int stage_no() { return (lg2(KS) - 1) * lg2(KS) / 2 + (lg2(KS) - 1 - lg2(J)); }
+
+    // Per-lane direction bits of every stage (bit set: this lane keeps the
+    // larger key, of x0 for the in-lane stages), fixed by the lane's slot.
     template <int KS>
-    __device__ static void bitonic(Key& x0, Key& x1, int s)
+    __device__ static uint32_t bitonic_dirs(int s)
     {
-        if constexpr (KS <= 2 * L) {
-            stage<KS, KS / 2>(x0, x1, s);
-            bitonic<KS * 2>(x0, x1, s);
-        }
+        if constexpr (KS <= 2 * L) return dirs_stage<KS, KS / 2>(s) | bitonic_dirs<KS * 2>(s);
+        else return 0u;
     }
     template <int KS, int J>
-    __device__ static void stage(Key& x0, Key& x1, int s)
+    __device__ static uint32_t dirs_stage(int s)
     {
         const bool up = ((2 * s) & KS) == 0;
-        if constexpr (J == 1) {
-            const Key lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
-            x0 = up ? lo : hi;
-            x1 = up ? hi : lo;
+        const bool keep_min = J == 1 ? up : ((((2 * s) & J) == 0) == up);
+        const uint32_t bit = keep_min ? 0u : (1u << stage_no<KS, J>());
+        if constexpr (J > 1) return bit | dirs_stage<KS, J / 2>(s);
+        else return bit;
+    }
+
+    // Bitonic sort, ascending, of the 2L keys of a frame: lane slot s holds
+    // elements 2s (x0) and 2s + 1 (x1).  Stages of size KS = 2, 4, ..., 2L.
+    // 32-bit keys take min or max in one v_med3 against 0 / ~0 chosen by the
+    // lane's direction bit.
+    template <int KS>
+    __device__ static void bitonic(Key& x0, Key& x1, int s, uint32_t dirs)
+    {
+        if constexpr (KS <= 2 * L) {
+            stage<KS, KS / 2>(x0, x1, s, dirs);
+            bitonic<KS * 2>(x0, x1, s, dirs);
+        }
+    }
+    __device__ static uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) { return max(min(a, b), min(max(a, b), c)); }
+    template <int KS, int J>
+    __device__ static void stage(Key& x0, Key& x1, int s, uint32_t dirs)
+    {
+        if constexpr (!FLOAT) {
+            const uint32_t bound = (uint32_t)(-(int32_t)((dirs >> stage_no<KS, J>()) & 1u));  // 0: min, ~0: max
+            if constexpr (J == 1) {
+                const Key a = x0, b = x1;
+                x0 = med3u(a, b, bound);
+                x1 = med3u(a, b, ~bound);
+            } else {
+                const Key y0 = xor_key<J / 2>(x0), y1 = xor_key<J / 2>(x1);
+                x0 = med3u(x0, y0, bound);
+                x1 = med3u(x1, y1, bound);
+                stage<KS, J / 2>(x0, x1, s, dirs);
+            }
         } else {
-            const Key y0 = xor_key<J / 2>(x0), y1 = xor_key<J / 2>(x1);
-            const bool keep_min = (((2 * s) & J) == 0) == up;
-            x0 = keep_min ? (y0 < x0 ? y0 : x0) : (y0 < x0 ? x0 : y0);
-            x1 = keep_min ? (y1 < x1 ? y1 : x1) : (y1 < x1 ? x1 : y1);
-            stage<KS, J / 2>(x0, x1, s);
+            const bool up = ((2 * s) & KS) == 0;
+            if constexpr (J == 1) {
+                const Key lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
+                x0 = up ? lo : hi;
+                x1 = up ? hi : lo;
+            } else {
+                const Key y0 = xor_key<J / 2>(x0), y1 = xor_key<J / 2>(x1);
+                const bool keep_min = (((2 * s) & J) == 0) == up;
+                x0 = keep_min ? (y0 < x0 ? y0 : x0) : (y0 < x0 ? x0 : y0);
+                x1 = keep_min ? (y1 < x1 ? y1 : x1) : (y1 < x1 ? x1 : y1);
+                stage<KS, J / 2>(x0, x1, s, dirs);
+            }
         }
     }
 };
@@ -479,6 +522,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     V pm = 0;
     bool valid = (slot == 0);
     uint64_t ptrs = 0;  // byte l: group slot owning this path's level-l buffer
+    const uint32_t dirs = K::template bitonic_dirs<2>(slot);  // sorting-network directions of this lane
     uint32_t ub[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) ub[i] = 0;
@@ -507,7 +551,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
         // which also names its parent slot and bit
         Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
         Key x1 = K::make_key(valid, (V)(pm + d1), 2 * slot + 1);
-        K::template bitonic<2>(x0, x1, slot);
+        K::template bitonic<2>(x0, x1, slot, dirs);
         const int src = gbase + (slot >> 1);
         const Key y0 = shfl_key(x0, src), y1 = shfl_key(x1, src);
         const Key mine = (slot & 1) ? y1 : y0;
