@@ -1,0 +1,50 @@
+// Device helper shared by the batch decoder and the server: applying an
+// accepted move w_p to a stage-2 column (Eq. (4): the centre moves to
+// c xor w_p; the stored -z changes sign on supp(w_p)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mpwsd {
+
+// Negate the int8 lanes of x whose bit is set in the low 4 bits of nib
+// (two's complement per byte, no carry between bytes).
+__device__ inline uint32_t neg_bytes(uint32_t x, uint32_t nib)
+{
+    const uint32_t one = ((nib & 15u) * 0x00204081u) & 0x01010101u;  // bit b -> byte b
+    const uint32_t t = x ^ (one * 0xFFu);
+    return ((t & 0x7F7F7F7Fu) + one) ^ (t & 0x80808080u);
+}
+
+// Flip the N centre bits cw[N/8] and the signs of zneg[N] (int8) on the
+// support of the packed move row mv[N/8]; 16 positions per step, the -z
+// column read and written in independent 16-byte pieces (zneg 16-byte aligned).
+__device__ inline void apply_move_i8(const uint8_t* __restrict__ mv, uint8_t* __restrict__ cw,
+                                     int8_t* __restrict__ zneg, int N)
+{
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    const uint16_t* m16 = reinterpret_cast<const uint16_t*>(mv);
+    uint16_t* c16 = reinterpret_cast<uint16_t*>(cw);
+    v4i_t* zp = reinterpret_cast<v4i_t*>(zneg);
+    for (int g = 0; g < N / 16; g += 4) {  // 64 positions at a time
+        uint32_t bits[4];
+        v4i_t zv[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            bits[h] = g + h < N / 16 ? m16[g + h] : 0u;
+            if (g + h < N / 16) zv[h] = zp[g + h];
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            if (g + h >= N / 16) continue;
+            c16[g + h] = (uint16_t)(c16[g + h] ^ bits[h]);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) zv[h][d] = (int)neg_bytes((uint32_t)zv[h][d], bits[h] >> (4 * d));
+            zp[g + h] = zv[h];
+        }
+    }
+}
+
+}  // namespace mpwsd

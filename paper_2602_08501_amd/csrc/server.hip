@@ -23,6 +23,7 @@
 #include <thread>
 #include <vector>
 
+#include "apply.h"
 #include "common.h"
 
 namespace {
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(256) void srv_resolve_kernel(
     int32_t* __restrict__ fdone, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
     int32_t* __restrict__ hdr, int cur, Record* __restrict__ rec)
 {
-    const int NB = N / 8, NWD = N / 32;
+    const int NB = N / 8;
     const int n = hdr[cur ? H_CNT1 : H_CNT0];
     int32_t* cnt_out = &hdr[cur ? H_CNT0 : H_CNT1];
     for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += gridDim.x * blockDim.x) {
@@ -147,18 +148,7 @@ __global__ __launch_bounds__(256) void srv_resolve_kernel(
             const int64_t p = (int64_t)(uint32_t)kv;
             const bool moved = kv != LLONG_MAX && S < 0 && p < P;
             if (moved) {
-                const uint32_t* mv = (const uint32_t*)(moves + (size_t)p * NB);
-                uint32_t* c32 = (uint32_t*)(cw + (size_t)col * NB);
-                int8_t* zc = zneg + (size_t)col * KP;
-                for (int wd = 0; wd < NWD; ++wd) {
-                    uint32_t bits = mv[wd];
-                    c32[wd] ^= bits;
-                    while (bits) {
-                        const int j = 32 * wd + __builtin_ctz(bits);
-                        zc[j] = (int8_t)(-zc[j]);
-                        bits &= bits - 1;
-                    }
-                }
+                mpwsd::apply_move_i8(moves + (size_t)p * NB, cw + (size_t)col * NB, zneg + (size_t)col * KP, N);
                 metric[col] += S;
                 citer[col] += 1;
             }

@@ -31,6 +31,7 @@
 #include <mutex>
 #include <vector>
 
+#include "apply.h"
 #include "common.h"
 
 namespace {
@@ -500,15 +501,6 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
 }
 
 // ---------------------------------------------------------------- int8 resolve
-// Negate the int8 lanes of x whose bit is set in the low 4 bits of nib
-// (two's complement per byte, no carry between bytes).
-__device__ inline uint32_t neg_bytes(uint32_t x, uint32_t nib)
-{
-    const uint32_t one = ((nib & 15u) * 0x00204081u) & 0x01010101u;  // bit b -> byte b
-    const uint32_t t = x ^ (one * 0xFFu);
-    return ((t & 0x7F7F7F7Fu) + one) ^ (t & 0x80808080u);
-}
-
 // Thread per active column: the search left the exact (S_min, p*) in the
 // key; when S_min < 0 the move is applied (centre bits flip, the stored -z
 // changes sign on the move's support, M += S, p* logged), the -z column being
@@ -538,26 +530,7 @@ __global__ __launch_bounds__(256) void resolve_i8_kernel(
                 if (p >= P) {
                     atomicAdd(&hdr[1], 1);
                 } else {
-                    const uint16_t* mv = (const uint16_t*)(moves + (size_t)p * NB);
-                    uint16_t* c16 = (uint16_t*)(cw + (size_t)col * NB);
-                    v4i* zp = (v4i*)(z + (size_t)col * KP);
-                    for (int g = 0; g < N / 16; g += 4) {  // 64 positions at a time
-                        uint32_t bits[4];
-                        v4i zv[4];
-#pragma unroll
-                        for (int h = 0; h < 4; ++h) {
-                            bits[h] = g + h < N / 16 ? mv[g + h] : 0u;
-                            if (g + h < N / 16) zv[h] = zp[g + h];
-                        }
-#pragma unroll
-                        for (int h = 0; h < 4; ++h) {
-                            if (g + h >= N / 16) continue;
-                            c16[g + h] = (uint16_t)(c16[g + h] ^ bits[h]);
-#pragma unroll
-                            for (int d = 0; d < 4; ++d) zv[h][d] = (int)neg_bytes((uint32_t)zv[h][d], bits[h] >> (4 * d));
-                            zp[g + h] = zv[h];
-                        }
-                    }
+                    mpwsd::apply_move_i8(moves + (size_t)p * NB, cw + (size_t)col * NB, z + (size_t)col * KP, N);
                     metric[col] += S;
                     if (out_moves) {
                         const int s = col / L, k = col % L;
