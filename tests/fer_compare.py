@@ -1,12 +1,14 @@
 """Frame-error-rate comparison of the int8 and binary32 forms of the decoder
-on the same received values, with the binary64 oracle on a subset.
+on the same received values, with the binary64 oracle on a subset.  Test
+infrastructure (it may call the oracle), run as a script from the repository
+root:
 
-    python -m paper_2602_08501_amd.fer --ebn0 2.0 2.5 3.0 3.5 4.0 --frames 262144
+    python -u tests/fer_compare.py --code rm37 --ebn0 2.0 2.5 3.0 3.5 4.0 --frames 262144
 
 Prints one JSON line per Eb/N0 point and a final summary line with the
 Eb/N0 at which each form reaches FER 1e-3 (log-linear interpolation) and the
 gap between the two forms in dB.  The oracle subset is decoded only when
---oracle-frames > 0 (test infrastructure, imported only then).
+--oracle-frames > 0.
 """
 from __future__ import annotations
 
@@ -14,14 +16,19 @@ import argparse
 import dataclasses
 import json
 import math
+import os
 import sys
 import time
 
 import numpy as np
 import torch
 
-from . import decoder as D
-from . import synth
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2602_08501_amd import decoder as D  # noqa: E402
+from paper_2602_08501_amd import synth  # noqa: E402
 
 
 def decode_gpu(code, wl, L, T, y, dtype, chunk=65536):
@@ -78,7 +85,7 @@ def main():
             res["_err_" + dt] = err
         res["disagree_i8_f32"] = int((res["_err_i8"] != res["_err_f32"]).sum())
         if args.oracle_frames > 0:
-            import oracle  # test infrastructure: the binary64 reference decoder
+            import oracle  # the binary64 reference decoder
             n = min(args.oracle_frames, args.frames)
             ref = oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, args.L, args.T, oracle.F64,
                                       y[:n].astype(np.float64), threads=args.oracle_threads)

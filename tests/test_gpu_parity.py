@@ -171,7 +171,7 @@ def test_empty_batch():
 
 
 # ---------------------------------------------------------------- pins on the device
-@pytest.mark.parametrize("m", [5, 7])
+@pytest.mark.parametrize("m", [5, 7, 8])
 def test_rm1_reaches_ml(m):
     """Sphere of RM(1, m) covers the code within two moves: T = 2 reaches ML."""
     say("case: rm1 ML", m)
