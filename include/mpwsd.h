@@ -173,6 +173,36 @@ int mpwsd_stage1_osd(int r, int m, int order, int L, const void* llr, int dtype,
                      uint8_t* anchors, int32_t* metric, hipStream_t stream);
 
 /*
+ * mpwsd_group_moves - the paired-half layout of a move table, for a faster
+ * int8 search over the same moves (same results, bit for bit).
+ *
+ * The search scores every move against every path's z (Eq. (5)).  A move of
+ * RM(r, m) that is a flat of EG(m, 2) (Sec. II-C: the minimum-weight words)
+ * lies in one half {x : u.x = c} of the positions for every normal u
+ * orthogonal to its direction space, and its translate by a unit vector e_i
+ * with u_i = 1 lies in the other half with the same pattern.  This call
+ * picks one normal per direction space and stores each pair of translates as
+ * ONE row of N/2 bits, so the search multiplies rows of length N/2 against
+ * both halves of every z: half the matrix-core work of the N-long rows.
+ *
+ * m: 7 or 8.  moves: HOST [P][N/8], the table given to mpwsd_decode_batch
+ * (canonical order of mpwsd_build_moves).  out: HOST buffer of cap_bytes
+ * bytes, or NULL for a query; it receives a self-contained byte layout that
+ * the caller copies verbatim to the device and passes as the grouped and
+ * grouped_chunks fields of a segment or server code.  *chunks and *bytes receive
+ * the number of 128-row chunks and the layout's size.  Moves keep their
+ * indices: the move logs and results do not change.
+ *
+ * Returns MPWSD_ERR_UNSUPPORTED when some move has no such normal or no
+ * translate partner in the table (e.g. radius >= 2 spheres, or RM(2, 7),
+ * whose 4 moves that fill a quarter of the positions have none): use the
+ * plain table then.  MPWSD_ERR_SIZE when out is too small (sizes are still
+ * reported).  Host-only, thread-safe; O(P N) time.
+ */
+int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t* out, size_t cap_bytes,
+                      int64_t* chunks, size_t* bytes);
+
+/*
  * One group of frames of one code for stage 2.
  */
 typedef struct mpwsd_segment {
@@ -195,6 +225,10 @@ typedef struct mpwsd_segment {
                                   ||y - x(c)||^2 in binary32); may be NULL */
     int32_t* out_moves;        /* device out [F][L][T]: accepted move index per
                                   path and iteration, -1 = none; may be NULL */
+    const uint8_t* grouped;    /* device copy of mpwsd_group_moves' layout of
+                                  this same table (256-byte aligned), or NULL;
+                                  used by the int8 search only */
+    int64_t grouped_chunks;    /* its chunk count (0 when grouped is NULL) */
 } mpwsd_segment;
 
 /*
@@ -325,6 +359,9 @@ typedef struct mpwsd_server_code {
     int crc_len;             /* CRC length (0: no CRC, every frame goes on) */
     uint32_t crc_poly;
     int capacity;            /* frames of this code in flight at most */
+    const uint8_t* grouped;  /* device copy of mpwsd_group_moves' layout of the
+                                table, or NULL (as in mpwsd_segment) */
+    int64_t grouped_chunks;
 } mpwsd_server_code;
 
 typedef struct mpwsd_result {

@@ -25,7 +25,7 @@ class Segment(ctypes.Structure):
     """struct mpwsd_segment."""
     _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("llr", _p), ("dtype", _i),
                 ("F", _i64), ("anchors", _p), ("crc_ok", _p), ("out_cw", _p), ("out_k", _p),
-                ("out_metric", _p), ("out_moves", _p)]
+                ("out_metric", _p), ("out_moves", _p), ("grouped", _p), ("grouped_chunks", _i64)]
 
 
 class VariantInfo(ctypes.Structure):
@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
 class ServerCode(ctypes.Structure):
     """struct mpwsd_server_code."""
     _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("L", _i), ("T", _i), ("crc_len", _i),
-                ("crc_poly", _u32), ("capacity", _i)]
+                ("crc_poly", _u32), ("capacity", _i), ("grouped", _p), ("grouped_chunks", _i64)]
 
 
 class Result(ctypes.Structure):
@@ -72,6 +72,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_last_error.argtypes = []
         lib.mpwsd_build_moves.argtypes = [_i, _i, _p, _sz, _p, _p, _p]
         lib.mpwsd_build_sphere.argtypes = [_i, _i, _i, _p, _sz, _p, _p, _p]
+        lib.mpwsd_group_moves.argtypes = [_i, _p, _i64, _p, _sz, _p, _p]
         lib.mpwsd_quantize_llr.argtypes = [_p, _i64, _f, _p, _p, _p]
         lib.mpwsd_stage1_scl.argtypes = [_i, _i, _i, _u32, _i, _p, _i, _i64, _p, _p, _p, _p]
         lib.mpwsd_stage1_osd.argtypes = [_i, _i, _i, _i, _p, _i, _i64, _p, _p, _p]
@@ -93,8 +94,8 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_server_poll.argtypes = [_p, ctypes.POINTER(Result), _i]
         lib.mpwsd_server_destroy.argtypes = [_p]
         lib.mpwsd_serve_trace.argtypes = [_p, _i64, _p, _p, _p, _p, ctypes.POINTER(_p), ctypes.POINTER(Result)]
-        for name in ("mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_quantize_llr", "mpwsd_stage1_scl",
-                     "mpwsd_stage1_osd", "mpwsd_decode_batch",
+        for name in ("mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_group_moves", "mpwsd_quantize_llr",
+                     "mpwsd_stage1_scl", "mpwsd_stage1_osd", "mpwsd_decode_batch",
                      "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
                      "mpwsd_graph_launch", "mpwsd_graph_destroy", "mpwsd_server_create", "mpwsd_server_submit",
                      "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"):
@@ -134,6 +135,13 @@ def mpwsd_build_sphere(r: int, m: int, radius: int, moves_ptr, cap_bytes: int):
     rc = load().mpwsd_build_sphere(r, m, radius, moves_ptr, cap_bytes, ctypes.byref(P), ctypes.byref(N),
                                    ctypes.byref(w))
     return rc, P.value, N.value, w.value
+
+
+def mpwsd_group_moves(m: int, moves_ptr, P: int, out_ptr, cap_bytes: int):
+    """Returns (rc, chunks, bytes); out_ptr may be None for a query."""
+    chunks, nbytes = ctypes.c_int64(), ctypes.c_size_t()
+    rc = load().mpwsd_group_moves(m, moves_ptr, P, out_ptr, cap_bytes, ctypes.byref(chunks), ctypes.byref(nbytes))
+    return rc, chunks.value, nbytes.value
 
 
 def mpwsd_quantize_llr(y_ptr, n: int, scale: float, q_ptr, bad_ptr, stream: int) -> int:

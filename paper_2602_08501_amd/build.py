@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmpwsd.so")
-SOURCES = ["moves.cpp", "graph.cpp", "stage1.hip", "osd.hip", "stage2.hip", "server.hip"]
+SOURCES = ["moves.cpp", "group.cpp", "graph.cpp", "stage1.hip", "osd.hip", "stage2.hip", "server.hip"]
 ARCH = os.environ.get("MPWSD_ARCH", "gfx950")
 
 

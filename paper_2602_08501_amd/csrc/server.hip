@@ -25,6 +25,7 @@
 
 #include "apply.h"
 #include "common.h"
+#include "group.h"
 
 namespace {
 
@@ -287,6 +288,14 @@ int check_codes(const mpwsd_server_code* codes, int ncodes)
         if (c.capacity < 1 || (int64_t)c.capacity * c.L > (1 << 26))
             return fail(MPWSD_ERR_ARG, "server code %d: bad capacity %d", i, c.capacity);
         if (!c.moves) return fail(MPWSD_ERR_ARG, "server code %d: moves is NULL", i);
+        if (c.grouped) {
+            if (c.m < 7) return fail(MPWSD_ERR_ARG, "server code %d: a paired-half table needs m = 7 or 8", i);
+            if (c.grouped_chunks < (c.P / 2 + 127) / 128 || c.grouped_chunks > mpwsd::group_max_chunks(c.m, c.P))
+                return fail(MPWSD_ERR_ARG, "server code %d: grouped_chunks %lld does not fit P = %lld", i,
+                            (long long)c.grouped_chunks, (long long)c.P);
+            if ((reinterpret_cast<uintptr_t>(c.grouped) & 255u) != 0)
+                return fail(MPWSD_ERR_ARG, "server code %d: grouped must be 256-byte aligned", i);
+        }
     }
     return MPWSD_OK;
 }
@@ -366,8 +375,8 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
                                act[c.cur], hdr, c.cur, c.at<Record>(c.lay.rec));
         }
         // one stage-2 iteration over every active path of this code
-        mpwsd::launch_search_i8(c.N, c.at<int8_t>(c.lay.zneg), c.c.moves, c.c.P, act[c.cur],
-                                hdr + (c.cur ? H_CNT1 : H_CNT0), c.at<long long>(c.lay.key), -1, 0, st);
+        mpwsd::launch_search_i8(c.N, c.at<int8_t>(c.lay.zneg), c.c.moves, c.c.P, c.c.grouped, c.c.grouped_chunks,
+                                act[c.cur], hdr + (c.cur ? H_CNT1 : H_CNT0), c.at<long long>(c.lay.key), -1, 0, st);
         const int cols = c.c.capacity * L;
         hipLaunchKernelGGL(srv_resolve_kernel, dim3((unsigned)std::min(((cols + 255) / 256), 2048)), dim3(256), 0,
                            st, L, c.c.T, c.N, c.KP, c.c.P, c.c.moves, c.at<uint8_t>(c.lay.cw),

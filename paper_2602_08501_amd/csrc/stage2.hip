@@ -33,6 +33,7 @@
 
 #include "apply.h"
 #include "common.h"
+#include "group.h"
 
 namespace {
 
@@ -415,6 +416,365 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
     }
 }
 
+// ---------------------------------------------------------------- paired-half int8 search
+// Tables of mpwsd_group_moves (layout in group.h): each 128-row chunk has one
+// normal u, and each row of N/2 bits is scored against both halves of every
+// column's z, {u.x = 0} and {u.x = 1}.  A lane group holds N/8 positions of
+// each half among its own N/4 positions, so the two half fragments are
+// gathered from the lane's canonical -z with one v_perm_b32 per output dword
+// whenever the normal changes.  Rows are sorted by canonical index for both
+// halves, so D = 128 S + row still picks the smallest index inside a
+// (chunk, half); across chunks and halves, equal minima are settled by the
+// canonical indices themselves.
+struct PwTable {
+    const int32_t* u;      // [chunks]
+    const uint8_t* rows;   // [chunks][128][N/2]
+    const int32_t* canon;  // [chunks][2][128]
+    const int32_t* sel;    // [N/4][N/4] byte selectors per normal
+    int chunks;
+};
+
+PwTable pw_table(const uint8_t* grouped, int m, int64_t chunks)
+{
+    const mpwsd::GroupLayout g = mpwsd::group_layout(m, chunks);
+    return PwTable{(const int32_t*)(grouped + g.u_off), grouped + g.rows_off, (const int32_t*)(grouped + g.canon_off),
+                   (const int32_t*)(grouped + g.sel_off), (int)chunks};
+}
+
+template <int WDW, int S>
+__device__ __forceinline__ void pw_gather(const uint32_t* zc, const uint32_t (&f0)[WDW], const uint32_t (&f1)[WDW],
+                                          v4i* zw0, v4i* zw1)
+{
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+        const int lo = ((k >> S) << (S + 1)) | (k & ((1 << S) - 1));
+        const int hi = lo + (1 << S);
+        zw0[k >> 2][k & 3] = (int)__builtin_amdgcn_perm(zc[hi], zc[lo], f0[k]);
+        zw1[k >> 2][k & 3] = (int)__builtin_amdgcn_perm(zc[hi], zc[lo], f1[k]);
+    }
+}
+
+template <int WDW, int S>
+__device__ __forceinline__ void pw_scatter(const v4i* zw0, const v4i* zw1, const uint32_t (&inv)[2 * WDW],
+                                           uint32_t* zc)
+{
+#pragma unroll
+    for (int k = 0; k < WDW; ++k) {
+        const int lo = ((k >> S) << (S + 1)) | (k & ((1 << S) - 1));
+        const int hi = lo + (1 << S);
+        zc[lo] = __builtin_amdgcn_perm((uint32_t)zw1[k >> 2][k & 3], (uint32_t)zw0[k >> 2][k & 3], inv[lo]);
+        zc[hi] = __builtin_amdgcn_perm((uint32_t)zw1[k >> 2][k & 3], (uint32_t)zw0[k >> 2][k & 3], inv[hi]);
+    }
+}
+
+// Re-gathers the half fragments of every column block for a new normal:
+// back to the canonical -z with the old normal's inverse selectors, then the
+// new halves (first == true: the canonical -z is loaded from z instead).
+// The selectors come from the table (scalar loads, wave-uniform).
+template <int N, int NC, int HW>
+__device__ __forceinline__ void pw_renormal(v4i (&zw)[2][NC][HW], const int32_t* __restrict__ sel, int old_u, int u,
+                                            bool first, int lg, const int8_t* __restrict__ z, const int (&colid)[NC])
+{
+    constexpr int LB = N / 4, LDW = LB / 4, WDW = LDW / 2, SELW = N / 4;
+    typedef const __attribute__((address_space(4))) int32_t* const_i32;
+    const const_i32 sn = (const_i32)sel + u * SELW;
+    const int Sn = sn[0];
+    uint32_t f0[WDW], f1[WDW];
+#pragma unroll
+    for (int q = 0; q < WDW; ++q) {
+        f0[q] = (uint32_t)sn[1 + q];
+        f1[q] = (uint32_t)sn[1 + WDW + q];
+    }
+    if (first) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            uint32_t zc[LDW];
+#pragma unroll
+            for (int d = 0; d < LDW / 4; ++d) {
+                v4i v = v4i{0, 0, 0, 0};
+                if (colid[c] >= 0) v = *(const v4i*)(z + (size_t)colid[c] * N + lg * LB + 16 * d);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) zc[4 * d + e] = (uint32_t)v[e];
+            }
+            switch (Sn) {
+            case 0: pw_gather<WDW, 0>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+            case 1: pw_gather<WDW, 1>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+            case 2: pw_gather<WDW, 2>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+            default:
+                if constexpr (WDW >= 8) pw_gather<WDW, 3>(zc, f0, f1, zw[0][c], zw[1][c]);
+                break;
+            }
+        }
+        return;
+    }
+    const const_i32 so = (const_i32)sel + old_u * SELW;
+    const int So = so[0];
+    uint32_t inv[LDW];
+#pragma unroll
+    for (int q = 0; q < LDW; ++q) inv[q] = (uint32_t)so[1 + 2 * WDW + q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        uint32_t zc[LDW];
+        switch (So) {
+        case 0: pw_scatter<WDW, 0>(zw[0][c], zw[1][c], inv, zc); break;
+        case 1: pw_scatter<WDW, 1>(zw[0][c], zw[1][c], inv, zc); break;
+        case 2: pw_scatter<WDW, 2>(zw[0][c], zw[1][c], inv, zc); break;
+        default:
+            if constexpr (WDW >= 8) pw_scatter<WDW, 3>(zw[0][c], zw[1][c], inv, zc);
+            break;
+        }
+        switch (Sn) {
+        case 0: pw_gather<WDW, 0>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+        case 1: pw_gather<WDW, 1>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+        case 2: pw_gather<WDW, 2>(zc, f0, f1, zw[0][c], zw[1][c]); break;
+        default:
+            if constexpr (WDW >= 8) pw_gather<WDW, 3>(zc, f0, f1, zw[0][c], zw[1][c]);
+            break;
+        }
+    }
+}
+
+// Chunks are swept in increasing order in groups of up to PW_GROUP chunks of
+// one normal.  A lane sees rows 16 tt + 4 lg + j (tt < 8, j < 4) of a chunk,
+// so its accumulator seed 32 q + 4 tt + j (q: the chunk's place in the group)
+// orders its rows of the group by chunk and row, i.e. canonically for both
+// halves; a group's minima are folded into the running best, with the
+// canonical indices from LDS, once per group.
+constexpr int PW_GROUP = 4;
+constexpr int PW_CSLOTS = 8;  // chunks whose canonical indices stay in LDS
+constexpr int PW_NBUF = 3;    // row buffers: two chunks are loaded ahead
+
+template <int N, int NC, int NWAVES>
+__device__ __forceinline__ void sweep_tile_pw(int8_t* __restrict__ lds, const int8_t* __restrict__ z, const PwTable& g,
+                                              const int32_t* __restrict__ act, int n, long long* __restrict__ keys,
+                                              int tile, int c0, int c1)
+{
+    constexpr int KW = N / 2;      // positions per half = bytes per row
+    constexpr int HW = KW / 64;    // MFMAs per 16 x 16 output tile and half
+    constexpr int CT = NWAVES * 16 * NC;
+    constexpr int NI = RC * KW / 1024;  // 1 KB direct-to-LDS loads per chunk of rows
+    static_assert(NI % NWAVES == 0 && 64 % NWAVES == 0, "loads per wave");
+    // vector-memory operations of one wave per chunk: its rows and its share
+    // of the canonical indices
+    constexpr int VM_PER_CHUNK = NI / NWAVES + 1;
+    // row buffer b (0 .. PW_NBUF-1), rows stored as in the table (swizzled
+    // segments); canonical indices of chunk k in slot k % PW_CSLOTS
+    auto buf = [lds](int b) { return lds + b * (RC * KW); };
+    auto cbuf = [lds](int slot) { return (int32_t*)(lds + PW_NBUF * (RC * KW)) + slot * (2 * RC); };
+    typedef __attribute__((address_space(3))) void* lds_ptr;
+    typedef const __attribute__((address_space(4))) int32_t* const_i32;
+    const const_i32 ut = (const_i32)g.u;  // normals: read-only, scalar loads
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    // LDS offset of this lane's A fragment hh of a 16-row tile (row li of the
+    // tile; the swizzle depends on li only, as tiles start at multiples of 16)
+    const int swz = (li / (256 / KW)) % (KW / 16);
+    int aoff[HW];
+#pragma unroll
+    for (int hh = 0; hh < HW; ++hh) aoff[hh] = li * KW + 16 * ((lg * (KW / 64) + hh) ^ swz);
+
+    // rows and canonical indices of a chunk are copied into LDS by the
+    // direct-to-LDS loads, PW_NBUF - 1 chunks ahead: the copy's latency is
+    // longer than one chunk's arithmetic
+    auto fetch = [&](int chunk, int b, int slot) {
+        for (int i = wave; i < NI; i += NWAVES)
+            __builtin_amdgcn_global_load_lds(g.rows + (size_t)chunk * RC * KW + i * 1024 + lane * 16,
+                                             (lds_ptr)(buf(b) + i * 1024), 16, 0, 0);
+        constexpr int CL = 64 / NWAVES;  // lanes per wave for the 1 KB of indices
+        if (lane < CL)
+            __builtin_amdgcn_global_load_lds(g.canon + (size_t)chunk * 2 * RC + wave * CL * 4 + lane * 4,
+                                             (lds_ptr)(cbuf(slot) + wave * CL * 4), 16, 0, 0);
+    };
+    // wait until at most n chunks' loads of this wave are in flight
+    auto wait_chunks = [](int n) {
+        constexpr int e = 0x7 << 4, l = 0xF << 8;  // no wait on export / LDS counters
+        if (n >= 1) {
+            constexpr int v = VM_PER_CHUNK;
+            __builtin_amdgcn_s_waitcnt((v & 0xF) | ((v >> 4) << 14) | e | l);
+        } else {
+            __builtin_amdgcn_s_waitcnt(e | l);
+        }
+    };
+
+    int colid[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int pos = tile * CT + wave * 16 * NC + c * 16 + li;
+        colid[c] = pos < n ? act[pos] : -1;
+    }
+
+    // the two half fragments of this wave's columns (the canonical -z: lane
+    // group lg holds positions [lg N/4, (lg + 1) N/4))
+    v4i zw[2][NC][HW];
+    // running best per column block: (S << 32 | canonical index)
+    long long run[NC];
+    // group minima per half and column block: 128 S + seed
+    int cm[2][NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        run[c] = LLONG_MAX;
+        cm[0][c] = cm[1][c] = INT_MAX;
+    }
+    int gs = c0, gq = 0;  // first chunk and size of the open group
+    auto flush = [&]() {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int seed = cm[h][c] & 127;
+                const int row = ((seed << 2) & 0x70) | (lg << 2) | (seed & 3);
+                const int slot = (gs + (seed >> 5)) & (PW_CSLOTS - 1);
+                const int cn = cbuf(slot)[h * RC + row];
+                const long long key = ((long long)(cm[h][c] >> 7) << 32) | (long long)(uint32_t)cn;
+                run[c] = key < run[c] ? key : run[c];
+                cm[h][c] = INT_MAX;
+            }
+    };
+
+    static_assert(PW_NBUF == 3, "two chunks in flight");
+    fetch(c0, 0, c0 & (PW_CSLOTS - 1));
+    if (c0 + 1 < c1) fetch(c0 + 1, 1, (c0 + 1) & (PW_CSLOTS - 1));
+    wait_chunks(c0 + 1 < c1 ? 1 : 0);
+    int u_k = ut[c0];
+    int u_n1 = c0 + 1 < c1 ? ut[c0 + 1] : 0;
+    int cur_u = u_k;
+    pw_renormal<N, NC, HW>(zw, g.sel, 0, u_k, true, lg, z, colid);
+    __syncthreads();
+    int b = 0;  // buffer of chunk k
+    for (int k = c0; k < c1; ++k) {
+        const int u = u_k;
+        int u_n2 = 0;
+        if (k + 2 < c1) {
+            const int b2 = b >= 1 ? b - 1 : 2;  // (b + 2) % 3
+            fetch(k + 2, b2, (k + 2) & (PW_CSLOTS - 1));
+            u_n2 = ut[k + 2];
+        }
+        if (u != cur_u || gq == PW_GROUP) {
+            if (gq > 0) flush();
+            gs = k;
+            gq = 0;
+        }
+        if (u != cur_u) {
+            pw_renormal<N, NC, HW>(zw, g.sel, cur_u, u, false, lg, z, colid);
+            cur_u = u;
+        }
+        // seeds 32 gq + 4 tt + j, advanced by 64-bit adds
+        unsigned long long s01 = ((unsigned long long)(32 * gq + 1) << 32) | (unsigned)(32 * gq);
+        unsigned long long s23 = ((unsigned long long)(32 * gq + 3) << 32) | (unsigned)(32 * gq + 2);
+        // two 16-row steps at a time: their 8 values per column and half are
+        // folded with 3 v_min3 that read matrix-core results and 1 that does
+        // not (the reading ones cost matrix-pipe time, see DESIGN notes on
+        // the epilogue); A fragments are read one pair of steps ahead
+        v4i an[2][HW];
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int hh = 0; hh < HW; ++hh) an[st][hh] = *(const v4i*)(buf(b) + st * 16 * KW + aoff[hh]);
+#pragma unroll 1
+        for (int tp = 0; tp < RC / 32; ++tp) {
+            v4i af[2][HW];
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int hh = 0; hh < HW; ++hh) af[st][hh] = an[st][hh];
+            if (tp + 1 < RC / 32) {
+#pragma unroll
+                for (int st = 0; st < 2; ++st)
+#pragma unroll
+                    for (int hh = 0; hh < HW; ++hh)
+                        an[st][hh] = *(const v4i*)(buf(b) + (2 * tp + 2 + st) * 16 * KW + aoff[hh]);
+            }
+            v4i acc[2][2][NC];  // [step][half][column block]
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const v4i seed = {(int)(uint32_t)s01, (int)(uint32_t)(s01 >> 32), (int)(uint32_t)s23,
+                                  (int)(uint32_t)(s23 >> 32)};
+                s01 += 0x0000000400000004ull;
+                s23 += 0x0000000400000004ull;
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        acc[st][h][c] = __builtin_amdgcn_mfma_i32_16x16x64_i8(af[st][0], zw[h][c][0], seed, 0, 0, 0);
+#pragma unroll
+                for (int hh = 1; hh < HW; ++hh)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int c = 0; c < NC; ++c)
+                            acc[st][h][c] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(af[st][hh], zw[h][c][hh], acc[st][h][c], 0, 0, 0);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const v4i& x = acc[0][h][c];
+                    const v4i& y = acc[1][h][c];
+                    int t1 = min(min(x[0], x[1]), x[2]);
+                    int t2 = min(min(x[3], y[0]), y[1]);
+                    asm volatile("" : "+v"(t1), "+v"(t2));
+                    int t3 = min(min(cm[h][c], y[2]), y[3]);
+                    asm volatile("" : "+v"(t3));
+                    cm[h][c] = min(min(t3, t1), t2);
+                }
+        }
+        ++gq;
+        // chunk k + 1 has landed in LDS (the direct loads count as vector
+        // memory operations) before any wave goes on; chunk k + 2 may not
+        wait_chunks(k + 2 < c1 ? 1 : 0);
+        u_k = u_n1;
+        u_n1 = u_n2;
+        b = b == 2 ? 0 : b + 1;
+        // every wave's LDS reads of this chunk are done (its buffer is the
+        // next one to be refilled) and the loads above have landed; a plain
+        // barrier, as a workgroup fence would also wait for chunk k + 2
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+    }
+    flush();
+    // lanes li, li+16, li+32, li+48 hold the same column
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        long long v = run[c];
+        long long o = __shfl_xor(v, 16);
+        v = o < v ? o : v;
+        o = __shfl_xor(v, 32);
+        v = o < v ? o : v;
+        if (lg == 0 && colid[c] >= 0) atomicMin(&keys[colid[c]], v);
+    }
+}
+
+// occupancy hint (minimum waves per SIMD) of the paired-half kernels: the two
+// halves double the accumulators, so at most 3 (170 VGPRs), 2 for 8 column
+// blocks or N = 256
+template <int N, int NC, int BPC>
+constexpr int pw_waves_per_simd() { return (NC >= 8 || N >= 256) ? 2 : (BPC > 3 ? 3 : BPC); }
+
+template <int N, int NC, int NWAVES, int BPC>
+__global__ __launch_bounds__(NWAVES * WAVE, (pw_waves_per_simd<N, NC, BPC>())) void search_pw_kernel(
+    const int8_t* __restrict__ z, PwTable g, const int32_t* __restrict__ act, const int32_t* __restrict__ count,
+    long long* __restrict__ keys)
+{
+    constexpr int CT = NWAVES * 16 * NC;
+    __shared__ __attribute__((aligned(16))) int8_t lds[PW_NBUF * RC * (N / 2) + PW_CSLOTS * 2 * RC * 4];
+    const int n = *count;
+    if (n <= 0) return;
+    const int tiles = (n + CT - 1) / CT;
+    const int C = g.chunks;
+    const int64_t U = (int64_t)tiles * C;
+    int64_t u0 = U * blockIdx.x / gridDim.x;
+    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    while (u0 < u1) {
+        const int tile = (int)(u0 / C);
+        const int c0 = (int)(u0 % C);
+        const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
+        u0 += c1 - c0;
+        sweep_tile_pw<N, NC, NWAVES>(lds, z, g, act, n, keys, tile, c0, c1);
+    }
+}
+
 // One code: (column tile x move chunk) units spread evenly over the grid.
 template <int N, int NC, int NWAVES, int BPC>
 __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
@@ -451,6 +811,8 @@ struct SegSearch {
     const int32_t* count;
     long long* keys;
     int N;
+    int grouped;  // 1: pw holds the paired-half table (N = 128 or 256)
+    PwTable pw;
 };
 constexpr int kMaxSeg = 4;
 struct MultiSearch {
@@ -462,6 +824,9 @@ template <int KPMAX, int NC, int NWAVES, int BPC>
 __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(MultiSearch ms)
 {
     constexpr int CT = NWAVES * 16 * NC;
+    // the plain layout of KPMAX is larger than the paired-half one of KPMAX
+    // with its chunk indices
+    static_assert(2 * RC * (KPMAX + 16) >= PW_NBUF * RC * (KPMAX / 2) + PW_CSLOTS * 2 * RC * 4, "LDS");
     __shared__ __attribute__((aligned(16))) int8_t lds[2 * RC * (KPMAX + 16)];
     int64_t ustart[kMaxSeg + 1];
     int nn[kMaxSeg], cc[kMaxSeg];
@@ -470,7 +835,7 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
     for (int i = 0; i < kMaxSeg; ++i) {
         const bool on = i < ms.nseg;
         nn[i] = on ? *ms.s[i].count : 0;
-        cc[i] = on ? (int)((ms.s[i].P + RC - 1) / RC) : 1;
+        cc[i] = on ? (ms.s[i].grouped ? ms.s[i].pw.chunks : (int)((ms.s[i].P + RC - 1) / RC)) : 1;
         const int tiles = (nn[i] + CT - 1) / CT;
         ustart[i + 1] = ustart[i] + (int64_t)tiles * cc[i];
     }
@@ -488,6 +853,14 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
         const int c0 = (int)(local % C);
         const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
         u0 += c1 - c0;
+        if (sg.grouped) {
+            if (sg.N == 128)
+                sweep_tile_pw<128, NC, NWAVES>(lds, sg.z, sg.pw, sg.act, nn[si], sg.keys, tile, c0, c1);
+            else if constexpr (KPMAX >= 256)
+                sweep_tile_pw<256, (NC > 4 ? 4 : NC), NWAVES>(lds, sg.z, sg.pw, sg.act, nn[si], sg.keys, tile, c0,
+                                                              c1);
+            continue;
+        }
         switch (sg.N) {
         case 32: sweep_tile<32, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
         case 64: sweep_tile<64, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
@@ -740,6 +1113,30 @@ void launch_search_i8_v(const int8_t* zneg, const uint8_t* moves, int64_t P, con
                        act, count, keys);
 }
 
+// paired-half search: column blocks per wave capped at 4 for N = 256 (VGPRs)
+template <int N, int V>
+void launch_search_pw_v(const int8_t* zneg, const PwTable& g, const int32_t* act, const int32_t* count,
+                        long long* keys, hipStream_t s, int grid)
+{
+    constexpr Variant v = kVariants[V];
+    constexpr int nc = (N >= 256 && v.nc > 4) ? 4 : v.nc;
+    hipLaunchKernelGGL((search_pw_kernel<N, nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s, zneg, g, act,
+                       count, keys);
+}
+
+template <int N>
+void launch_search_pw_n(const int8_t* zneg, const PwTable& g, const int32_t* act, const int32_t* count,
+                        long long* keys, hipStream_t s, int variant, int grid)
+{
+    switch (variant) {
+    case 0: launch_search_pw_v<N, 0>(zneg, g, act, count, keys, s, grid); break;
+    case 1: launch_search_pw_v<N, 1>(zneg, g, act, count, keys, s, grid); break;
+    case 2: launch_search_pw_v<N, 2>(zneg, g, act, count, keys, s, grid); break;
+    case 3: launch_search_pw_v<N, 3>(zneg, g, act, count, keys, s, grid); break;
+    default: launch_search_pw_v<N, 4>(zneg, g, act, count, keys, s, grid); break;
+    }
+}
+
 template <int N>
 void launch_search_i8_n(const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
                         const int32_t* count, long long* keys, hipStream_t s, int variant, int grid)
@@ -854,8 +1251,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
         if (sg.dtype == MPWSD_F32)
             launch_search_f32(w, sg, t, s, device_cus() * 4);
         else
-            mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, w.act[t & 1], w.hdr + 2 + t,
-                                    (long long*)w.key64, variant[t], blocks_per_cu[t], s);
+            mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, sg.grouped, sg.grouped_chunks,
+                                    w.act[t & 1], w.hdr + 2 + t, (long long*)w.key64, variant[t], blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         seg_resolve(sg, L, T, w, t, s);
     }
@@ -880,6 +1277,8 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         g.P = segs[i].P;
         g.keys = (long long*)w[i].key64;
         g.N = 1 << segs[i].m;
+        g.grouped = segs[i].grouped && (g.N == 128 || g.N == 256);
+        if (g.grouped) g.pw = pw_table(segs[i].grouped, segs[i].m, segs[i].grouped_chunks);
         maxN = std::max(maxN, g.N);
     }
     for (int t = 0; t < T; ++t) {
@@ -925,6 +1324,15 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
             return fail(MPWSD_ERR_ARG, "segment %d: null pointer", i);
         if (check_ptrs && (reinterpret_cast<uintptr_t>(s.moves) & 3u) != 0)
             return fail(MPWSD_ERR_ARG, "segment %d: moves must be 4-byte aligned", i);
+        if (s.grouped) {
+            if (s.m < 7)
+                return fail(MPWSD_ERR_ARG, "segment %d: a paired-half table needs m = 7 or 8", i);
+            if (s.grouped_chunks < (s.P / 2 + 127) / 128 || s.grouped_chunks > mpwsd::group_max_chunks(s.m, s.P))
+                return fail(MPWSD_ERR_ARG, "segment %d: grouped_chunks %lld does not fit P = %lld", i,
+                            (long long)s.grouped_chunks, (long long)s.P);
+            if ((reinterpret_cast<uintptr_t>(s.grouped) & 255u) != 0)
+                return fail(MPWSD_ERR_ARG, "segment %d: grouped must be 256-byte aligned", i);
+        }
     }
     return MPWSD_OK;
 }
@@ -934,16 +1342,26 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
 namespace mpwsd {
 int device_cu_count() { return device_cus(); }
 
-void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
-                      const int32_t* count, long long* keys, int variant, int blocks_per_cu, hipStream_t s)
+void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const uint8_t* grouped,
+                      int64_t grouped_chunks, const int32_t* act, const int32_t* count, long long* keys, int variant,
+                      int blocks_per_cu, hipStream_t s)
 {
     const int cus = device_cus();
-    const int KP = kpad(N);
+    const bool pw = grouped && (N == 128 || N == 256);
     const int var = variant >= 0 ? variant : default_variant(N);
     // workgroups per CU: requested, else the variant's default capped by how
     // many fit in the 160 KB LDS of a CU
-    const int lds_fit = (160 * 1024) / (2 * RC * (KP + 16));
+    const int lds_ws = pw ? PW_NBUF * RC * (N / 2) + PW_CSLOTS * 2 * RC * 4 : 2 * RC * (kpad(N) + 16);
+    const int lds_fit = (160 * 1024) / lds_ws;
     const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
+    if (pw) {
+        const PwTable g = pw_table(grouped, N == 128 ? 7 : 8, grouped_chunks);
+        if (N == 128)
+            launch_search_pw_n<128>(zneg, g, act, count, keys, s, var, grid);
+        else
+            launch_search_pw_n<256>(zneg, g, act, count, keys, s, var, grid);
+        return;
+    }
     switch (N) {
     case 32: launch_search_i8_n<32>(zneg, moves, P, act, count, keys, s, var, grid); break;
     case 64: launch_search_i8_n<64>(zneg, moves, P, act, count, keys, s, var, grid); break;

@@ -34,7 +34,7 @@ class Server:
         arr = (ServerCode * len(codes))()
         for i, (c, sp) in enumerate(zip(codes, specs)):
             arr[i] = ServerCode(c.r, c.m, c.moves.data_ptr(), c.P, sp["L"], sp["T"], sp.get("crc_len", 6),
-                                sp.get("crc_poly", synth.CRC6_POLY), sp["capacity"])
+                                sp.get("crc_poly", synth.CRC6_POLY), sp["capacity"], c.grouped_ptr(), c.grouped_chunks)
         self._arr = arr
         need = _lib.load().mpwsd_server_arena_bytes(arr, len(codes))
         if need == 0:

@@ -14,7 +14,8 @@ from paper_2602_08501_amd._lib import Segment
 def test_library_exports_every_declared_call():
     lib = _lib.load()
     names = _lib.header_functions()
-    assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_quantize_llr",
+    assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_group_moves",
+                          "mpwsd_quantize_llr",
                           "mpwsd_stage1_osd",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
@@ -103,6 +104,11 @@ def test_decode_batch_validates_before_enqueue():
         ([_seg(llr=None)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(moves=0x1001)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(r=2, m=6, P=2604 + 291647)], 8, 8, _lib.MPWSD_ERR_ARG),   # not a sphere size of RM(2,6)
+        # paired-half layouts: only for m >= 7, with a chunk count that fits P, 256-byte aligned
+        ([_seg(r=2, m=6, P=2604, grouped=0x100000, grouped_chunks=11)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(grouped=0x100000, grouped_chunks=368)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(grouped=0x100000, grouped_chunks=370 + 128 + 1)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(grouped=0x100080, grouped_chunks=373)], 8, 8, _lib.MPWSD_ERR_ARG),
     ]
     for segs, L, T, code in cases:
         if segs[-1].llr and segs[-1].moves % 4 == 0:  # size query ignores pointers
@@ -111,6 +117,7 @@ def test_decode_batch_validates_before_enqueue():
     # every sphere size of RM(2,6) is accepted: S_1, S_2 and S_3 without the zero word
     for P in (2604, 2604 + 291648, 2604 + 291648 + 888832):
         assert _lib.mpwsd_workspace_bytes([_seg(r=2, m=6, P=P)], 8, 8) > 0, _lib.last_error()
+    assert _lib.mpwsd_workspace_bytes([_seg(grouped=0x100000, grouped_chunks=373)], 8, 8) == ok
     # workspace too small / missing / misaligned
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10000, ok - 1, None, None) == _lib.MPWSD_ERR_SIZE
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, None, ok, None, None) == _lib.MPWSD_ERR_SIZE
