@@ -664,27 +664,10 @@ __device__ __forceinline__ void sweep_tile_pw(int8_t* __restrict__ lds, const in
         unsigned long long s23 = ((unsigned long long)(32 * gq + 3) << 32) | (unsigned)(32 * gq + 2);
         // two 16-row steps at a time: their 8 values per column and half are
         // folded with 3 v_min3 that read matrix-core results and 1 that does
-        // not (the reading ones cost matrix-pipe time, see DESIGN notes on
-        // the epilogue); A fragments are read one pair of steps ahead
-        v4i an[2][HW];
-#pragma unroll
-        for (int st = 0; st < 2; ++st)
-#pragma unroll
-            for (int hh = 0; hh < HW; ++hh) an[st][hh] = *(const v4i*)(buf(b) + st * 16 * KW + aoff[hh]);
-#pragma unroll 1
-        for (int tp = 0; tp < RC / 32; ++tp) {
-            v4i af[2][HW];
-#pragma unroll
-            for (int st = 0; st < 2; ++st)
-#pragma unroll
-                for (int hh = 0; hh < HW; ++hh) af[st][hh] = an[st][hh];
-            if (tp + 1 < RC / 32) {
-#pragma unroll
-                for (int st = 0; st < 2; ++st)
-#pragma unroll
-                    for (int hh = 0; hh < HW; ++hh)
-                        an[st][hh] = *(const v4i*)(buf(b) + (2 * tp + 2 + st) * 16 * KW + aoff[hh]);
-            }
+        // not (the reading ones cost matrix-pipe time); the A fragments of
+        // the next pair of steps are read while this pair computes, into
+        // alternating registers
+        auto pair = [&](const v4i (&af)[2][HW]) {
             v4i acc[2][2][NC];  // [step][half][column block]
 #pragma unroll
             for (int st = 0; st < 2; ++st) {
@@ -719,7 +702,23 @@ __device__ __forceinline__ void sweep_tile_pw(int8_t* __restrict__ lds, const in
                     asm volatile("" : "+v"(t3));
                     cm[h][c] = min(min(t3, t1), t2);
                 }
-        }
+        };
+        auto load_pair = [&](int tp, v4i (&a)[2][HW]) {
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+#pragma unroll
+                for (int hh = 0; hh < HW; ++hh) a[st][hh] = *(const v4i*)(buf(b) + (2 * tp + st) * 16 * KW + aoff[hh]);
+        };
+        static_assert(RC / 32 == 4, "four pairs of steps per chunk");
+        v4i a0[2][HW], a1[2][HW];
+        load_pair(0, a0);
+        load_pair(1, a1);
+        pair(a0);
+        load_pair(2, a0);
+        pair(a1);
+        load_pair(3, a1);
+        pair(a0);
+        pair(a1);
         ++gq;
         // chunk k + 1 has landed in LDS (the direct loads count as vector
         // memory operations) before any wave goes on; chunk k + 2 may not
