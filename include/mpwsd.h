@@ -253,6 +253,14 @@ size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T);
  * mode S_p is summed in binary32 in ascending j and the final metric is
  * ||y - x(c)||^2 summed in binary32 in ascending j.
  *
+ * Paths of one frame that reach the same centre are merged (unless
+ * mpwsd_options.no_merge): what a path does next depends on its centre
+ * alone, so after each iteration a path that moved onto the centre of a
+ * path that did not move stops, and one that moved onto the centre of a
+ * moved path of smaller index follows that path; neither is searched again.
+ * At the end a follower is given its leader's later moves, centre and
+ * metric, so every output equals that of searching all paths.
+ *
  * Several int8 segments (up to 4, e.g. codes of different lengths) are
  * decoded together: each iteration searches the failing paths of all of them
  * in ONE launch of the search kernel.
@@ -260,7 +268,8 @@ size_t mpwsd_workspace_bytes(const mpwsd_segment* segs, int nseg, int L, int T);
  * segs[nseg]: host array.  All segments must use the same dtype.
  * ws: device workspace of ws_bytes >= mpwsd_workspace_bytes(...) bytes.
  * stats: device out int32[2 + T] or NULL: [0] = frames sent to stage 2
- *        (summed over segments), [1 + t] = paths searched in iteration t,
+ *        (summed over segments), [1 + t] = paths searched in iteration t
+ *        (after merging),
  *        [1 + T] = internal consistency failures (0 expected).
  * Supported: 5 <= m <= 8, 1 <= r < m, 1 <= L <= 32, 1 <= T <= 64.
  */
@@ -299,6 +308,10 @@ typedef struct mpwsd_options {
                                        overrides search_variant */
     const int* iter_blocks_per_cu;  /* NULL, or T host entries overriding
                                        blocks_per_cu per iteration */
+    int no_merge;                   /* 1: search every active path in every
+                                       iteration, also paths of one frame
+                                       that have reached the same centre
+                                       (same outputs, more searched paths) */
 } mpwsd_options;
 
 /*

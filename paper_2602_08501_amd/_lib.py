@@ -36,7 +36,8 @@ class VariantInfo(ctypes.Structure):
 class Options(ctypes.Structure):
     """struct mpwsd_options."""
     _fields_ = [("search_variant", _i), ("blocks_per_cu", _i), ("events", ctypes.POINTER(_p)),
-                ("iter_variant", ctypes.POINTER(_i)), ("iter_blocks_per_cu", ctypes.POINTER(_i))]
+                ("iter_variant", ctypes.POINTER(_i)), ("iter_blocks_per_cu", ctypes.POINTER(_i)),
+                ("no_merge", _i)]
 
 
 class ServerCode(ctypes.Structure):
@@ -175,10 +176,11 @@ def mpwsd_decode_batch(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, s
 
 
 def mpwsd_decode_batch_ex(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, variant=-1,
-                          blocks_per_cu=0, event_handles=None, stream=None) -> int:
-    """variant / blocks_per_cu: one value, or a list of T values (one per iteration)."""
+                          blocks_per_cu=0, event_handles=None, stream=None, merge=True) -> int:
+    """variant / blocks_per_cu: one value, or a list of T values (one per iteration).
+    merge=False searches every active path (sets mpwsd_options.no_merge)."""
     arr = segments_array(segs)
-    opt = Options(-1, 0, None, None, None)
+    opt = Options(-1, 0, None, None, None, 0 if merge else 1)
     if isinstance(variant, (list, tuple)):
         iv = (_i * len(variant))(*variant)
         opt.iter_variant = ctypes.cast(iv, ctypes.POINTER(_i))

@@ -50,6 +50,7 @@ struct SegWs {
     uint64_t* key64;  // [F*L] per-column minimum: int8 (S << 32 | p) as int64,
                       // float (orderable(S) << 32 | p) as uint64
     int32_t* metric;  // [F*L] int8: M; float: unused
+    int32_t* tag;     // [F*L] path state for the merging of equal centres
     uint8_t* cw;      // [F*L][N/8] centres
     void* z;          // [F*L][KP] int8 -z (negated) or [F*L][N] float z
     size_t bytes;
@@ -72,6 +73,7 @@ SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
     w.act[0] = (int32_t*)take(sizeof(int32_t) * C);
     w.act[1] = (int32_t*)take(sizeof(int32_t) * C);
     w.key64 = (uint64_t*)take(sizeof(uint64_t) * C);
+    w.tag = (int32_t*)take(sizeof(int32_t) * C);
     if (sg.dtype == MPWSD_I8) {
         w.metric = (int32_t*)take(sizeof(int32_t) * C);
         w.z = take(C * (size_t)kpad(N));
@@ -168,7 +170,8 @@ __global__ __launch_bounds__(256) void init_kernel(
     const void* __restrict__ llr, const uint8_t* __restrict__ anchors, int64_t F, int L, int T, int N, int KP,
     int32_t* __restrict__ hdr, const int32_t* __restrict__ slot, const int32_t* __restrict__ fid,
     int32_t* __restrict__ act0, uint64_t* __restrict__ key64, int32_t* __restrict__ metric,
-    uint8_t* __restrict__ cw, void* __restrict__ zbuf, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
+    int32_t* __restrict__ tag, uint8_t* __restrict__ cw, void* __restrict__ zbuf, uint8_t* __restrict__ out_cw,
+    int32_t* __restrict__ out_k,
     int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves, int32_t* __restrict__ stats)
 {
     const int PP = KP / 16;  // pieces per item (4, 8 or 16: an item's pieces share a wave)
@@ -254,6 +257,7 @@ __global__ __launch_bounds__(256) void init_kernel(
             if (inpos) *(uint16_t*)(cw + (size_t)col * NB + 2 * piece) = (uint16_t)bits;
             if (piece == 0) {
                 act0[col] = (int32_t)col;
+                tag[col] = 0;
                 key64[col] = FLOAT ? ~0ull : (uint64_t)LLONG_MAX;
                 if (!FLOAT) metric[col] = part;
             }
@@ -877,12 +881,13 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
 // key; when S_min < 0 the move is applied (centre bits flip, the stored -z
 // changes sign on the move's support, M += S, p* logged), the -z column being
 // read and written in independent 16-byte pieces, and the column is appended
-// to the next active list with one atomic per wave.
+// to the next active list with one atomic per wave (with merging, it is only
+// marked as moved and the merge pass builds the list).
 __global__ __launch_bounds__(256) void resolve_i8_kernel(
     int8_t* __restrict__ z, uint8_t* __restrict__ cw, int32_t* __restrict__ metric, const uint8_t* __restrict__ moves,
     int N, int KP, int64_t P, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
     int32_t* __restrict__ hdr, int t, int T, long long* __restrict__ keys, const int32_t* __restrict__ fid, int L,
-    int32_t* __restrict__ out_moves)
+    int32_t* __restrict__ out_moves, int32_t* __restrict__ tag)
 {
     const int lane = threadIdx.x & 63;
     const int n = hdr[2 + t];
@@ -911,6 +916,10 @@ __global__ __launch_bounds__(256) void resolve_i8_kernel(
                     moved = true;
                 }
             }
+        }
+        if (tag) {  // the merge pass builds the next list
+            if (moved) tag[col] = t + 1;
+            continue;
         }
         const uint64_t bal = __ballot(moved);
         int wbase = 0;
@@ -999,7 +1008,8 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
 __global__ __launch_bounds__(256) void resolve_f32_kernel(
     float* __restrict__ z, uint8_t* __restrict__ cw, const uint8_t* __restrict__ moves, int N, int64_t P,
     const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out, int32_t* __restrict__ hdr, int t, int T,
-    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves)
+    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves,
+    int32_t* __restrict__ tag)
 {
     const int lane = threadIdx.x & 63;
     const int NB = N / 8, NWD = N / 32;
@@ -1040,11 +1050,120 @@ __global__ __launch_bounds__(256) void resolve_f32_kernel(
                 }
             }
         }
+        if (tag) {  // the merge pass builds the next list
+            if (moved) tag[col] = t + 1;
+            continue;
+        }
         const uint64_t bal = __ballot(moved);
         int wbase = 0;
         if (lane == 0 && bal) wbase = atomicAdd(&hdr[2 + t + 1], __popcll(bal));
         wbase = __shfl(wbase, 0);
         if (moved) act_out[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = col;
+    }
+}
+
+// ---------------------------------------------------------------- merging
+// Paths of one frame that reach the same centre have the same future: the
+// search of an iteration, the move it picks and whether the path stops are
+// functions of the centre alone (z and M are).  So after the resolve of
+// iteration t < T - 1, each path that moved is compared with the other paths
+// of its frame:
+//   * at the centre of a path that did not move (it searched there, or at an
+//     equal centre, and found no improving move) it would stop at t + 1: it
+//     is not searched again, and its state is already final;
+//   * at the centre of a moved path of smaller index ("leader") it follows
+//     that path: it is not searched again, and records (t + 1, leader) so
+//     that the finishing pass gives it the leader's later moves, final
+//     centre and metric;
+//   * otherwise it goes on to iteration t + 1.
+// Decisions, metrics and move logs are those of searching every path (ties
+// go to the smaller path index, and a follower never has a smaller index
+// than its leader); only the searched paths per iteration drop.
+//
+// tag[column]: >= 0 the next iteration the column would be searched in (a
+// column in the active list of iteration t has tag t; one that moved in t
+// has t + 1; a smaller value means it stopped), < 0 a follower,
+// -1 - (first skipped iteration << 5 | leader).
+//
+// Lanes are paths: LP = L rounded up to a power of two lanes per frame,
+// 64 / LP frames per wave; centres are compared word by word across lanes.
+template <int NW>
+__global__ __launch_bounds__(256) void merge_kernel(int32_t* __restrict__ hdr, int t, int L, int LP,
+                                                    int32_t* __restrict__ tag, const uint32_t* __restrict__ cw,
+                                                    int32_t* __restrict__ act_out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per_wave = WAVE / LP;
+    const int g = lane / LP, k = lane % LP, gbase = g * LP;
+    const int64_t f2 = hdr[0];
+    const int64_t step = (int64_t)gridDim.x * (blockDim.x / WAVE) * per_wave;
+    for (int64_t s0 = ((int64_t)blockIdx.x * (blockDim.x / WAVE) + wave) * per_wave; s0 < f2; s0 += step) {
+        const int64_t s = s0 + g;
+        const bool ok = k < L && s < f2;
+        const int64_t col = s * L + k;
+        const int tg = ok ? tag[col] : -1;
+        const bool moved = ok && tg == t + 1;
+        const bool still = ok && tg >= 0 && tg <= t;
+        const uint64_t mv = __ballot(moved);
+        if (mv == 0) continue;
+        const uint64_t st = __ballot(still);
+        uint32_t c[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) c[w] = (moved || still) ? cw[(size_t)col * NW + w] : 0u;
+        bool stop = false;
+        int lead = -1;
+        for (int j = 0; j < L; ++j) {
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) eq = (__shfl(c[w], gbase + j) == c[w]) && eq;
+            if (moved && eq && j != k) {
+                if ((st >> (gbase + j)) & 1) stop = true;
+                else if (((mv >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
+            }
+        }
+        const bool keep = moved && !stop && lead < 0;
+        if (moved && !stop && lead >= 0) tag[col] = -1 - (((t + 1) << 5) | lead);
+        const uint64_t kb = __ballot(keep);
+        int wb = 0;
+        if (lane == 0 && kb) wb = atomicAdd(&hdr[2 + t + 1], __popcll(kb));
+        wb = __shfl(wb, 0);
+        if (keep) act_out[wb + __popcll(kb & ((1ull << lane) - 1ull))] = (int32_t)col;
+    }
+}
+
+// After the last iteration: each follower takes its leader's moves from the
+// iteration it stopped being searched, following the chain of leaders (a
+// leader may itself have started following a path of smaller index later),
+// and the final centre and metric of the end of the chain.  Each thread
+// writes only its own column and reads log entries and states that no thread
+// writes here.
+__global__ __launch_bounds__(256) void merge_finish_kernel(const int32_t* __restrict__ hdr, int L, int T, int NB,
+                                                           const int32_t* __restrict__ tag, uint8_t* __restrict__ cw,
+                                                           int32_t* __restrict__ metric, const int32_t* __restrict__ fid,
+                                                           int32_t* __restrict__ out_moves)
+{
+    const int64_t cols = (int64_t)hdr[0] * L;
+    for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < cols;
+         col += (int64_t)gridDim.x * blockDim.x) {
+        const int tg = tag[col];
+        if (tg >= 0) continue;
+        const int64_t s = col / L;
+        const int k = (int)(col % L);
+        const size_t f = (size_t)fid[s];
+        const int v = -1 - tg;
+        int from = v >> 5, cur = v & 31;
+        for (int hop = 0; hop < L; ++hop) {
+            const int ct = tag[s * L + cur];
+            const int upto = ct < 0 ? ((-1 - ct) >> 5) : T;
+            if (out_moves)
+                for (int u = from; u < upto; ++u)
+                    out_moves[(f * L + k) * T + u] = out_moves[(f * L + cur) * T + u];
+            if (ct >= 0) break;
+            from = upto;
+            cur = (-1 - ct) & 31;
+        }
+        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = cw[((size_t)s * L + cur) * NB + b];
+        if (metric) metric[col] = metric[s * L + cur];
     }
 }
 
@@ -1206,31 +1325,61 @@ void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 8 * device_cus()));
     if (fl)
         hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
-                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.tag, w.cw, w.z, sg.out_cw, sg.out_k,
                            sg.out_metric, sg.out_moves, stats);
     else
         hipLaunchKernelGGL(init_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
-                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.cw, w.z, sg.out_cw, sg.out_k,
+                           w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.tag, w.cw, w.z, sg.out_cw, sg.out_k,
                            sg.out_metric, sg.out_moves, stats);
 }
 
-void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, hipStream_t s)
+int lanes_per_frame(int L)
+{
+    int lp = 1;
+    while (lp < L) lp <<= 1;
+    return lp;
+}
+
+// Resolve of iteration t; with merge (t < T - 1), the merge pass then builds
+// the next active list.
+void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, bool merge, hipStream_t s)
 {
     const int N = 1 << sg.m, KP = kpad(N);
     const int resolve_blocks = device_cus() * 4;
+    merge = merge && t + 1 < T;
+    int32_t* tag = merge ? w.tag : nullptr;
     if (sg.dtype == MPWSD_F32)
         hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves, N,
                            sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (unsigned long long*)w.key64, w.fid,
-                           L, sg.out_moves);
+                           L, sg.out_moves, tag);
     else
         hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
                            sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
-                           (long long*)w.key64, w.fid, L, sg.out_moves);
+                           (long long*)w.key64, w.fid, L, sg.out_moves, tag);
+    if (!merge) return;
+    const int lp = lanes_per_frame(L);
+    const int64_t frames_per_block = 4 * (WAVE / lp);
+    const unsigned blocks = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 4 * device_cus()));
+    const uint32_t* cw = (const uint32_t*)w.cw;
+    int32_t* out = w.act[(t + 1) & 1];
+    switch (N) {
+    case 32: hipLaunchKernelGGL(merge_kernel<1>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
+    case 64: hipLaunchKernelGGL(merge_kernel<2>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
+    case 128: hipLaunchKernelGGL(merge_kernel<4>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
+    default: hipLaunchKernelGGL(merge_kernel<8>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
+    }
 }
 
-void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, hipStream_t s)
+void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, bool merge, int32_t* stats, hipStream_t s)
 {
     const int N = 1 << sg.m;
+    if (merge && T > 1) {
+        const int64_t cols = sg.F * (int64_t)L;
+        const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cols + 255) / 256, 4 * device_cus()));
+        hipLaunchKernelGGL(merge_finish_kernel, dim3(fb), dim3(256), 0, s, w.hdr, L, T, N / 8, w.tag, w.cw,
+                           sg.dtype == MPWSD_I8 ? w.metric : nullptr, w.fid, sg.out_moves);
+    }
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
     if (sg.dtype == MPWSD_F32)
         hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N, w.metric,
@@ -1241,7 +1390,7 @@ void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
 }
 
 int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, bool zero_stats,
-                hipEvent_t* ev, const int* variant, const int* blocks_per_cu, hipStream_t s)
+                hipEvent_t* ev, const int* variant, const int* blocks_per_cu, bool merge, hipStream_t s)
 {
     const int N = 1 << sg.m;
     seg_prologue(sg, L, T, w, stats, zero_stats, s);
@@ -1253,9 +1402,9 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
             mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, sg.grouped, sg.grouped_chunks,
                                     w.act[t & 1], w.hdr + 2 + t, (long long*)w.key64, variant[t], blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
-        seg_resolve(sg, L, T, w, t, s);
+        seg_resolve(sg, L, T, w, t, merge, s);
     }
-    seg_epilogue(sg, L, T, w, stats, s);
+    seg_epilogue(sg, L, T, w, merge, stats, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch: %s", hipGetErrorString(e));
     return MPWSD_OK;
@@ -1263,7 +1412,7 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
 
 // Several int8 segments: every iteration's search of all codes is ONE launch.
 int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w, int32_t* stats, hipEvent_t* ev,
-              const int* variant, const int* blocks_per_cu, hipStream_t s)
+              const int* variant, const int* blocks_per_cu, bool merge, hipStream_t s)
 {
     MultiSearch base{};
     int maxN = 0;
@@ -1292,10 +1441,10 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         if (ms.nseg > 0) launch_search_multi(ms, maxN, variant[t], blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         for (int i = 0; i < nseg; ++i)
-            if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, s);
+            if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, merge, s);
     }
     for (int i = 0; i < nseg; ++i)
-        if (segs[i].F > 0) seg_epilogue(segs[i], L, T, w[i], stats, s);
+        if (segs[i].F > 0) seg_epilogue(segs[i], L, T, w[i], merge, stats, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch: %s", hipGetErrorString(e));
     return MPWSD_OK;
@@ -1397,6 +1546,7 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
             return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_decode_batch: blocks_per_cu %d (iteration %d) out of range",
                                bpc[t], t);
     }
+    const bool merge = !(opt && opt->no_merge);
     size_t need = 0;
     for (int i = 0; i < nseg; ++i) need += carve(segs[i], L, T, nullptr).bytes;
     if (!ws || ws_bytes < need)
@@ -1416,12 +1566,12 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
     }
     if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8)
         return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr,
-                         variant.data(), bpc.data(), stream);
+                         variant.data(), bpc.data(), merge, stream);
     bool first = true;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
         hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
-        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant.data(), bpc.data(), stream);
+        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant.data(), bpc.data(), merge, stream);
         first = false;
         if (rc != MPWSD_OK) return rc;
     }

@@ -173,20 +173,23 @@ class Stage2:
         return segs
 
     def run(self, llrs, anchors, crc_oks, stream=None, events=None, variant=-1, blocks_per_cu=0,
-            raw_stream=None):
+            raw_stream=None, merge=True):
         """events: optional list of 2 * T * nseg recorded torch.cuda.Event
         (enable_timing=True); re-recorded around every search launch.
         variant / blocks_per_cu: one value, or T values (per iteration).
         raw_stream: a hipStream_t handle (int) to enqueue on instead of a
-        torch stream (used while recording a graph)."""
+        torch stream (used while recording a graph).
+        merge=False searches every active path, also paths of a frame that
+        reached the same centre (same outputs, more searched paths)."""
         segs = self._segs(llrs, anchors, crc_oks)
         st = raw_stream if raw_stream is not None else _stream(stream)
         per_iter = isinstance(variant, (list, tuple)) or isinstance(blocks_per_cu, (list, tuple))
-        if events is None and not per_iter and variant < 0 and blocks_per_cu == 0:
+        if events is None and not per_iter and variant < 0 and blocks_per_cu == 0 and merge:
             check(_lib.mpwsd_decode_batch(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
                                           self.stats.data_ptr(), st))
         else:
             check(_lib.mpwsd_decode_batch_ex(segs, self.L, self.T, self.ws_ptr, self.ws_bytes,
                                              self.stats.data_ptr(), variant, blocks_per_cu,
-                                             None if events is None else [e.cuda_event for e in events], st))
+                                             None if events is None else [e.cuda_event for e in events], st,
+                                             merge=merge))
         return self.outs

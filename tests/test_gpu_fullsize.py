@@ -14,6 +14,8 @@ from paper_2602_08501_amd import autotune
 from paper_2602_08501_amd import decoder as D
 from paper_2602_08501_amd import synth
 
+from merge_rule import searched_counts
+
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
@@ -75,10 +77,11 @@ def test_rm37_bench_size():
     say("  tiles", tiles, "stats", stats.tolist())
     fail = np.nonzero(out["crc_ok"] == 0)[0]
     assert stats[0] == len(fail) and stats[1] == len(fail) * L and stats[-1] == 0
-    # every logged move count matches the next iteration's searched paths
-    logs = out["moves"][fail]
-    for t in range(1, T):
-        assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
+    # the searched paths per iteration replay from the logged moves (one path
+    # per distinct centre of a frame)
+    anc = np.unpackbits(out["anchors"][fail], axis=-1, bitorder="little")
+    supp = oracle.moves(wl.r, wl.m)[0]
+    assert np.array_equal(stats[1:1 + T], searched_counts(anc, out["moves"][fail], supp))
     rng = np.random.default_rng(0)
     rows = np.sort(np.concatenate([rng.choice(fail, 160, replace=False),
                                    rng.choice(np.nonzero(out["crc_ok"])[0], 64, replace=False),

@@ -18,6 +18,8 @@ import oracle
 from paper_2602_08501_amd import decoder as D
 from paper_2602_08501_amd import synth
 
+from merge_rule import searched_counts
+
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
@@ -44,7 +46,7 @@ def workload(wl, seed, F, f0=0):
     return c, y, q
 
 
-def run_gpu(wl, L, T, obs, dtype, crc=True, anchors=None, crc_ok=None):
+def run_gpu(wl, L, T, obs, dtype, crc=True, anchors=None, crc_ok=None, merge=True):
     cd = code(wl.r, wl.m)
     llr = torch.from_numpy(obs).to(DEV)
     if anchors is None:
@@ -53,7 +55,7 @@ def run_gpu(wl, L, T, obs, dtype, crc=True, anchors=None, crc_ok=None):
     else:
         s1 = None
     st = D.Stage2([(cd, obs.shape[0])], L, T, dtype, DEV)
-    out = st.run([llr], [anchors], [crc_ok])[0]
+    out = st.run([llr], [anchors], [crc_ok], merge=merge)[0]
     torch.cuda.synchronize()
     return s1, out, st.stats.cpu().numpy()
 
@@ -113,11 +115,12 @@ E2E = [
 
 @pytest.mark.parametrize("name,wl,L,T,F", E2E, ids=[e[0] for e in E2E])
 @pytest.mark.parametrize("dtype", ["i8", "f32"])
-def test_decode_parity(name, wl, L, T, F, dtype):
-    say("case: decode", name, dtype)
+@pytest.mark.parametrize("merge", [True, False], ids=["merge", "nomerge"])
+def test_decode_parity(name, wl, L, T, F, dtype, merge):
+    say("case: decode", name, dtype, "merge" if merge else "no merge")
     c, y, q = workload(wl, 2, F)
     obs = q if dtype == "i8" else y
-    s1, out, stats = run_gpu(wl, L, T, obs, dtype)
+    s1, out, stats = run_gpu(wl, L, T, obs, dtype, merge=merge)
     mode = oracle.INT if dtype == "i8" else oracle.F32
     ref = oracle.decode_batch(wl.r, wl.m, wl.crc_len, wl.crc_poly, L, T, mode, obs.astype(np.float64), threads=8)
     assert np.array_equal(s1["crc_ok"].cpu().numpy(), ref["crc_ok"])
@@ -135,10 +138,16 @@ def test_decode_parity(name, wl, L, T, F, dtype):
         assert np.array_equal(met.view(np.float32), ref["metric"].astype(np.float32))
         ed64 = np.array([oracle.metric(oracle.F64, y[f].astype(np.float64), ref["c"][f]) for f in range(F)])
         assert np.allclose(met.view(np.float32).astype(np.float64), ed64, rtol=1e-5, atol=0)
-    # iteration counts reported by the device equal the oracle's searched paths
-    logs = ref["logs"][ref["crc_ok"] == 0]
-    for t in range(1, T):
-        assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
+    # searched paths per iteration: the oracle's moved paths without merging,
+    # one path per distinct centre of a frame with it
+    fail = ref["crc_ok"] == 0
+    logs = ref["logs"][fail]
+    if merge:
+        supp = oracle.moves(wl.r, wl.m)[0]
+        assert np.array_equal(stats[1:1 + T], searched_counts(ref["anchors"][fail], logs, supp))
+    else:
+        for t in range(1, T):
+            assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
     say("  failing frames", nfail, "searched per iteration", stats[1:1 + T].tolist())
 
 

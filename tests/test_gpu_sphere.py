@@ -17,6 +17,8 @@ import oracle
 from paper_2602_08501_amd import decoder as D
 from paper_2602_08501_amd import synth
 
+from merge_rule import searched_counts
+
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
@@ -112,9 +114,9 @@ def test_sphere_decode_parity(name, wl, radius, L, T, F, dtype):
         assert np.array_equal(met, ref["metric"].astype(np.int32))
     else:
         assert np.array_equal(met.view(np.float32), ref["metric"].astype(np.float32))
-    logs = ref["logs"][ref["crc_ok"] == 0]
-    for t in range(1, T):
-        assert stats[1 + t] == int((logs[:, :, t - 1] >= 0).sum())
+    fail = ref["crc_ok"] == 0
+    logs = ref["logs"][fail]
+    assert np.array_equal(stats[1:1 + T], searched_counts(ref["anchors"][fail], logs, supp))
     used = logs[logs >= 0]
     outside = int((used >= oracle.moves(wl.r, wl.m)[0].shape[0]).sum())
     say("  failing", nfail, "searched", stats[1:1 + T].tolist(), "moves outside shell 1:", outside)
