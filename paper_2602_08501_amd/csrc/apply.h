@@ -47,4 +47,23 @@ __device__ inline void apply_move_i8(const uint8_t* __restrict__ mv, uint8_t* __
     }
 }
 
+// Flip the signs of zneg[N] (int8, 16-byte aligned) on the positions whose
+// bit is set in the packed move row held in registers, mb[N/32].
+template <int NW>
+__device__ inline void flip_z_i8(const uint32_t (&mb)[NW], int8_t* __restrict__ zneg)
+{
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
+    v4i_t* zp = reinterpret_cast<v4i_t*>(zneg);
+    v4i_t zv[2 * NW];
+#pragma unroll
+    for (int g = 0; g < 2 * NW; ++g) zv[g] = zp[g];
+#pragma unroll
+    for (int g = 0; g < 2 * NW; ++g) {
+        const uint32_t bits = mb[g >> 1] >> (16 * (g & 1));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) zv[g][d] = (int)neg_bytes((uint32_t)zv[g][d], bits >> (4 * d));
+        zp[g] = zv[g];
+    }
+}
+
 }  // namespace mpwsd

@@ -5,24 +5,27 @@
 // holds the centre c (packed bits), z = llr * (1 - 2c) and the metric.  The
 // move search of one iteration is the contraction S = W Z of the move matrix
 // W (P x N, 0/1) with the z columns, followed by an argmin over P:
-//   * int8 form: W is kept bit-packed in HBM; each workgroup unpacks a chunk
-//     of 128 moves into LDS once and all its waves feed it to
-//     v_mfma_i32_16x16x64_i8 against z fragments that stay in VGPRs for the
-//     whole sweep.  The epilogue keeps a running minimum with v_min3 and, per
-//     128-move chunk, folds (minimum << 16 | chunk) into one int32 key, so
-//     the first chunk holding the column minimum survives; the exact move is
-//     recovered afterwards by rescoring that single chunk.
+//   * int8 form: chunks of 128 moves are staged in LDS and fed to
+//     v_mfma_i32_16x16x64_i8 against -z fragments that stay in VGPRs for the
+//     whole sweep.  The accumulator is seeded so that each result reads
+//     128 S + (row within the chunk), a running v_min3 keeps the smallest,
+//     and per chunk the exact key (S << 32 | p) is formed from the row
+//     index, so the smallest p attaining the minimum wins.  Two move tables:
+//     the bit-packed one (unpacked into LDS per chunk), and the paired-half
+//     one of mpwsd_group_moves (rows of N/2 bytes, each scoring a move and
+//     its translate against the two halves of z; copied verbatim into LDS).
 //   * float form: the same contraction summed sequentially in binary32 in
 //     ascending position order on the vector ALUs, with the exact move index
 //     carried in a 64-bit key.
 // Work is split over (column tile x move chunk) units spread evenly over a
 // fixed, device-filling grid; split results meet in an atomicMin per column,
 // which is order independent, so the result does not depend on the split.
-// After each search a resolve pass applies the moves, logs them and
-// compacts the columns that moved into the next iteration's active list
-// (a column that did not move can never move again).  All counts live in
-// device memory, so T iterations enqueue without any host round trip and
-// can be captured in a HIP graph.
+// After each search a resolve pass applies the moves, logs them and builds
+// the next iteration's active list (a column that did not move can never
+// move again); a merge pass drops the columns whose centre another column of
+// the frame already holds.  All counts live in device memory, so T
+// iterations enqueue without any host round trip and can be captured in a
+// HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,10 +46,13 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------- workspace
 struct SegWs {
-    int32_t* hdr;     // [0]=F2 [1]=err [2..2+T] active count per iteration
+    int32_t* hdr;     // [0]=F2 [1]=err, then per iteration t <= T the pair
+                      // [ncol(t)] columns to search, [ncol(t)+1] frames
+                      // holding them (kept with merging), 8-byte aligned
     int32_t* fid;     // [F] compacted failing frames
     int32_t* slot;    // [F] frame -> compacted slot (-1 when decided)
     int32_t* act[2];  // [F*L] active column lists (ping-pong)
+    int32_t* fl[2];   // [F] frames with an active column (merging; ping-pong)
     uint64_t* key64;  // [F*L] per-column minimum: int8 (S << 32 | p) as int64,
                       // float (orderable(S) << 32 | p) as uint64
     int32_t* metric;  // [F*L] int8: M; float: unused
@@ -58,6 +64,11 @@ struct SegWs {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+int hdr_len(int T) { return 4 + 2 * T; }
+
+// index in hdr of the column count of iteration t (the frame count follows)
+__host__ __device__ constexpr int ncol(int t) { return 2 + 2 * t; }
+
 int kpad(int N) { return N < 64 ? 64 : N; }
 
 SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
@@ -67,11 +78,13 @@ SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
     SegWs w{};
     size_t off = 0;
     auto take = [&](size_t b) { uint8_t* p = base ? base + off : nullptr; off += align_up(b); return p; };
-    w.hdr = (int32_t*)take(sizeof(int32_t) * (size_t)(4 + T));
+    w.hdr = (int32_t*)take(sizeof(int32_t) * (size_t)hdr_len(T));
     w.fid = (int32_t*)take(sizeof(int32_t) * F);
     w.slot = (int32_t*)take(sizeof(int32_t) * F);
     w.act[0] = (int32_t*)take(sizeof(int32_t) * C);
     w.act[1] = (int32_t*)take(sizeof(int32_t) * C);
+    w.fl[0] = (int32_t*)take(sizeof(int32_t) * F);
+    w.fl[1] = (int32_t*)take(sizeof(int32_t) * F);
     w.key64 = (uint64_t*)take(sizeof(uint64_t) * C);
     w.tag = (int32_t*)take(sizeof(int32_t) * C);
     if (sg.dtype == MPWSD_I8) {
@@ -154,7 +167,7 @@ __global__ void stats_zero_kernel(int32_t* stats, int n)
 __device__ inline void stats_add(const int32_t* __restrict__ hdr, int T, int32_t* __restrict__ stats)
 {
     const int t = threadIdx.x;
-    if (t < T) atomicAdd(&stats[1 + t], hdr[2 + t]);
+    if (t < T) atomicAdd(&stats[1 + t], hdr[ncol(t)]);
     if (t == 0) atomicAdd(&stats[1 + T], hdr[1]);
 }
 
@@ -180,7 +193,7 @@ __global__ __launch_bounds__(256) void init_kernel(
     const int64_t part1 = F * PP;
     const int64_t total = part1 + nfail * L * PP;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        hdr[2] = (int32_t)(nfail * L);
+        hdr[ncol(0)] = (int32_t)(nfail * L);
         if (stats) atomicAdd(&stats[0], (int32_t)nfail);
     }
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ((total + 63) & ~int64_t(63));
@@ -881,16 +894,16 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
 // key; when S_min < 0 the move is applied (centre bits flip, the stored -z
 // changes sign on the move's support, M += S, p* logged), the -z column being
 // read and written in independent 16-byte pieces, and the column is appended
-// to the next active list with one atomic per wave (with merging, it is only
-// marked as moved and the merge pass builds the list).
+// to the next active list with one atomic per wave.  (This is the form that
+// searches every path; resolve_merge_kernel is the one that merges.)
 __global__ __launch_bounds__(256) void resolve_i8_kernel(
     int8_t* __restrict__ z, uint8_t* __restrict__ cw, int32_t* __restrict__ metric, const uint8_t* __restrict__ moves,
     int N, int KP, int64_t P, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
     int32_t* __restrict__ hdr, int t, int T, long long* __restrict__ keys, const int32_t* __restrict__ fid, int L,
-    int32_t* __restrict__ out_moves, int32_t* __restrict__ tag)
+    int32_t* __restrict__ out_moves)
 {
     const int lane = threadIdx.x & 63;
-    const int n = hdr[2 + t];
+    const int n = hdr[ncol(t)];
     const int NB = N / 8;
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
@@ -917,13 +930,9 @@ __global__ __launch_bounds__(256) void resolve_i8_kernel(
                 }
             }
         }
-        if (tag) {  // the merge pass builds the next list
-            if (moved) tag[col] = t + 1;
-            continue;
-        }
         const uint64_t bal = __ballot(moved);
         int wbase = 0;
-        if (lane == 0 && bal) wbase = atomicAdd(&hdr[2 + t + 1], __popcll(bal));
+        if (lane == 0 && bal) wbase = atomicAdd(&hdr[ncol(t + 1)], __popcll(bal));
         wbase = __shfl(wbase, 0);
         if (moved) act_out[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = col;
     }
@@ -954,7 +963,7 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
     __shared__ float zs[N * CT];
     __shared__ uint8_t sup[MC * N];  // ascending supports
     __shared__ int wts[MC];           // their weights
-    const int n = hdr[2 + t];
+    const int n = hdr[ncol(t)];
     if (n <= 0) return;
     const int lane = threadIdx.x;
     const int tiles = (n + CT - 1) / CT;
@@ -1008,12 +1017,11 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
 __global__ __launch_bounds__(256) void resolve_f32_kernel(
     float* __restrict__ z, uint8_t* __restrict__ cw, const uint8_t* __restrict__ moves, int N, int64_t P,
     const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out, int32_t* __restrict__ hdr, int t, int T,
-    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves,
-    int32_t* __restrict__ tag)
+    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int32_t* __restrict__ out_moves)
 {
     const int lane = threadIdx.x & 63;
     const int NB = N / 8, NWD = N / 32;
-    const int n = hdr[2 + t];
+    const int n = hdr[ncol(t)];
     const int stride = gridDim.x * blockDim.x;
     for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += stride) {
         const int pos = base + lane;
@@ -1050,66 +1058,132 @@ __global__ __launch_bounds__(256) void resolve_f32_kernel(
                 }
             }
         }
-        if (tag) {  // the merge pass builds the next list
-            if (moved) tag[col] = t + 1;
-            continue;
-        }
         const uint64_t bal = __ballot(moved);
         int wbase = 0;
-        if (lane == 0 && bal) wbase = atomicAdd(&hdr[2 + t + 1], __popcll(bal));
+        if (lane == 0 && bal) wbase = atomicAdd(&hdr[ncol(t + 1)], __popcll(bal));
         wbase = __shfl(wbase, 0);
         if (moved) act_out[wbase + __popcll(bal & ((1ull << lane) - 1ull))] = col;
     }
 }
 
-// ---------------------------------------------------------------- merging
+// ---------------------------------------------------------------- resolve with merging
 // Paths of one frame that reach the same centre have the same future: the
 // search of an iteration, the move it picks and whether the path stops are
-// functions of the centre alone (z and M are).  So after the resolve of
-// iteration t < T - 1, each path that moved is compared with the other paths
-// of its frame:
+// functions of the centre alone (z and M are).  This resolve applies the
+// moves of iteration t frame by frame and, for t < T - 1, compares each path
+// that moved with the other paths of its frame:
 //   * at the centre of a path that did not move (it searched there, or at an
 //     equal centre, and found no improving move) it would stop at t + 1: it
 //     is not searched again, and its state is already final;
 //   * at the centre of a moved path of smaller index ("leader") it follows
-//     that path: it is not searched again, and records (t + 1, leader) so
-//     that the finishing pass gives it the leader's later moves, final
-//     centre and metric;
+//     that path: it is not searched again, and select gives it the leader's
+//     later moves;
 //   * otherwise it goes on to iteration t + 1.
 // Decisions, metrics and move logs are those of searching every path (ties
-// go to the smaller path index, and a follower never has a smaller index
-// than its leader); only the searched paths per iteration drop.
+// go to the smaller path index, and a leader always has a smaller index than
+// its followers); only the searched paths per iteration drop.
 //
-// tag[column]: >= 0 the next iteration the column would be searched in (a
-// column in the active list of iteration t has tag t; one that moved in t
-// has t + 1; a smaller value means it stopped), < 0 a follower,
-// -1 - (first skipped iteration << 5 | leader).
+// tag[column]: >= 0 the last iteration the column was (or, equal to t + 1,
+// will be) searched in; < 0 a follower, -1 - (first skipped iteration << 5 |
+// leader).  A column is searched in iteration t iff its tag is t.
 //
 // Lanes are paths: LP = L rounded up to a power of two lanes per frame,
-// 64 / LP frames per wave; centres are compared word by word across lanes.
-template <int NW>
-__global__ __launch_bounds__(256) void merge_kernel(int32_t* __restrict__ hdr, int t, int L, int LP,
-                                                    int32_t* __restrict__ tag, const uint32_t* __restrict__ cw,
-                                                    int32_t* __restrict__ act_out)
+// 64 / LP frames per wave; the new centres stay in registers and are compared
+// word by word across the frame's lanes.  The frames with a column left to
+// search form the next frame list (all failing frames in iteration 0).
+template <bool FLOAT, int NW>
+__global__ __launch_bounds__(256) void resolve_merge_kernel(
+    void* __restrict__ zbuf, uint32_t* __restrict__ cw, int32_t* __restrict__ metric,
+    const uint8_t* __restrict__ moves, int KP, int64_t P, int32_t* __restrict__ hdr, int t, int T,
+    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int LP,
+    int32_t* __restrict__ out_moves, int32_t* __restrict__ tag, const int32_t* __restrict__ fl_in,
+    int32_t* __restrict__ fl_out, int32_t* __restrict__ act_out)
 {
+    constexpr int N = 32 * NW;
+    typedef int v4i_t __attribute__((ext_vector_type(4)));
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per_wave = WAVE / LP;
     const int g = lane / LP, k = lane % LP, gbase = g * LP;
-    const int64_t f2 = hdr[0];
-    const int64_t step = (int64_t)gridDim.x * (blockDim.x / WAVE) * per_wave;
-    for (int64_t s0 = ((int64_t)blockIdx.x * (blockDim.x / WAVE) + wave) * per_wave; s0 < f2; s0 += step) {
-        const int64_t s = s0 + g;
-        const bool ok = k < L && s < f2;
-        const int64_t col = s * L + k;
-        const int tg = ok ? tag[col] : -1;
-        const bool moved = ok && tg == t + 1;
-        const bool still = ok && tg >= 0 && tg <= t;
-        const uint64_t mv = __ballot(moved);
-        if (mv == 0) continue;
-        const uint64_t st = __ballot(still);
-        uint32_t c[NW];
+    const bool merge = t + 1 < T;
+    const int nfr = fl_in ? hdr[ncol(t) + 1] : hdr[0];
+    const int step = gridDim.x * (blockDim.x / WAVE) * per_wave;
+    for (int i0 = (blockIdx.x * (blockDim.x / WAVE) + wave) * per_wave; i0 < nfr; i0 += step) {
+        const int i = i0 + g;
+        const bool ok = i < nfr && k < L;
+        const int s = ok ? (fl_in ? fl_in[i] : i) : 0;
+        const int64_t col = (int64_t)s * L + k;
+        // every load that does not need the key is issued at once
+        int tg = -1, M = 0, f = 0;
+        unsigned long long key = 0;
+        uint32_t c[NW] = {};
+        v4i_t zv[2 * NW];
+        if (ok) {
+            tg = tag[col];
+            key = keys[col];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) c[w] = (moved || still) ? cw[(size_t)col * NW + w] : 0u;
+            for (int w = 0; w < NW; ++w) c[w] = cw[(size_t)col * NW + w];
+            if (!FLOAT) {
+                M = metric[col];
+                const v4i_t* zp = reinterpret_cast<const v4i_t*>((const int8_t*)zbuf + (size_t)col * KP);
+#pragma unroll
+                for (int q = 0; q < 2 * NW; ++q) zv[q] = zp[q];
+            }
+            if (out_moves) f = fid[s];
+        }
+        bool moved = false;
+        int64_t p = 0;
+        int S = 0;
+        if (tg == t) {
+            if (FLOAT) {
+                keys[col] = ~0ull;
+                // orderable(S) < orderable(+0) = 0x80000000 <=> S < 0
+                moved = key != ~0ull && (uint32_t)(key >> 32) < 0x80000000u;
+            } else {
+                keys[col] = (unsigned long long)LLONG_MAX;
+                S = (int)((long long)key >> 32);
+                moved = (long long)key != LLONG_MAX && S < 0;
+            }
+            p = (int64_t)(key & 0xFFFFFFFFull);
+            if (moved && p >= P) {
+                atomicAdd(&hdr[1], 1);
+                moved = false;
+            }
+        }
+        if (moved) {
+            const uint32_t* mv = reinterpret_cast<const uint32_t*>(moves + (size_t)p * (N / 8));
+            uint32_t mb[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) mb[w] = mv[w];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                c[w] ^= mb[w];
+                cw[(size_t)col * NW + w] = c[w];
+            }
+            if (FLOAT) {
+                float* zc = (float*)zbuf + (size_t)col * N;
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+                    for (uint32_t bits = mb[w]; bits; bits &= bits - 1) {
+                        const int j = 32 * w + __builtin_ctz(bits);
+                        zc[j] = -zc[j];
+                    }
+            } else {
+                v4i_t* zp = reinterpret_cast<v4i_t*>((int8_t*)zbuf + (size_t)col * KP);
+#pragma unroll
+                for (int q = 0; q < 2 * NW; ++q) {
+                    const uint32_t bits = mb[q >> 1] >> (16 * (q & 1));
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) zv[q][d] = (int)mpwsd::neg_bytes((uint32_t)zv[q][d], bits >> (4 * d));
+                    zp[q] = zv[q];
+                }
+                metric[col] = M + S;
+            }
+            if (out_moves) out_moves[((size_t)f * L + k) * T + t] = (int32_t)p;
+        }
+        if (!merge) continue;
+        const uint64_t mvb = __ballot(moved);
+        if (mvb == 0) continue;
+        const uint64_t stb = __ballot(tg >= 0 && !moved);
         bool stop = false;
         int lead = -1;
         for (int j = 0; j < L; ++j) {
@@ -1117,76 +1191,71 @@ __global__ __launch_bounds__(256) void merge_kernel(int32_t* __restrict__ hdr, i
 #pragma unroll
             for (int w = 0; w < NW; ++w) eq = (__shfl(c[w], gbase + j) == c[w]) && eq;
             if (moved && eq && j != k) {
-                if ((st >> (gbase + j)) & 1) stop = true;
-                else if (((mv >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
+                if ((stb >> (gbase + j)) & 1) stop = true;
+                else if (((mvb >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
             }
         }
         const bool keep = moved && !stop && lead < 0;
-        if (moved && !stop && lead >= 0) tag[col] = -1 - (((t + 1) << 5) | lead);
+        if (keep) tag[col] = t + 1;
+        else if (moved && !stop) tag[col] = -1 - (((t + 1) << 5) | lead);
+        // next column and frame lists: one 64-bit atomic per wave on the
+        // (frames << 32 | columns) pair of iteration t + 1
         const uint64_t kb = __ballot(keep);
-        int wb = 0;
-        if (lane == 0 && kb) wb = atomicAdd(&hdr[2 + t + 1], __popcll(kb));
-        wb = __shfl(wb, 0);
-        if (keep) act_out[wb + __popcll(kb & ((1ull << lane) - 1ull))] = (int32_t)col;
-    }
-}
-
-// After the last iteration: each follower takes its leader's moves from the
-// iteration it stopped being searched, following the chain of leaders (a
-// leader may itself have started following a path of smaller index later),
-// and the final centre and metric of the end of the chain.  Each thread
-// writes only its own column and reads log entries and states that no thread
-// writes here.
-__global__ __launch_bounds__(256) void merge_finish_kernel(const int32_t* __restrict__ hdr, int L, int T, int NB,
-                                                           const int32_t* __restrict__ tag, uint8_t* __restrict__ cw,
-                                                           int32_t* __restrict__ metric, const int32_t* __restrict__ fid,
-                                                           int32_t* __restrict__ out_moves)
-{
-    const int64_t cols = (int64_t)hdr[0] * L;
-    for (int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; col < cols;
-         col += (int64_t)gridDim.x * blockDim.x) {
-        const int tg = tag[col];
-        if (tg >= 0) continue;
-        const int64_t s = col / L;
-        const int k = (int)(col % L);
-        const size_t f = (size_t)fid[s];
-        const int v = -1 - tg;
-        int from = v >> 5, cur = v & 31;
-        for (int hop = 0; hop < L; ++hop) {
-            const int ct = tag[s * L + cur];
-            const int upto = ct < 0 ? ((-1 - ct) >> 5) : T;
-            if (out_moves)
-                for (int u = from; u < upto; ++u)
-                    out_moves[(f * L + k) * T + u] = out_moves[(f * L + cur) * T + u];
-            if (ct >= 0) break;
-            from = upto;
-            cur = (-1 - ct) & 31;
-        }
-        for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = cw[((size_t)s * L + cur) * NB + b];
-        if (metric) metric[col] = metric[s * L + cur];
+        const uint64_t fb = __ballot(k == 0 && ((kb >> gbase) & ((1ull << LP) - 1ull)) != 0);
+        unsigned long long base = 0;
+        if (lane == 0 && kb)
+            base = atomicAdd(reinterpret_cast<unsigned long long*>(hdr + ncol(t + 1)),
+                             ((unsigned long long)__popcll(fb) << 32) | (unsigned long long)__popcll(kb));
+        base = __shfl(base, 0);
+        if (keep) act_out[(int)(uint32_t)base + __popcll(kb & ((1ull << lane) - 1ull))] = (int32_t)col;
+        if ((fb >> lane) & 1) fl_out[(int)(base >> 32) + __popcll(fb & ((1ull << lane) - 1ull))] = s;
     }
 }
 
 // ---------------------------------------------------------------- select
 // Alg. 1 return step: per failing frame, the path of smallest metric, ties
-// to the smallest path index.
+// to the smallest path index.  With merging (tag != NULL) a follower ends
+// where its chain of leaders ends, at the same metric and a larger index, so
+// it is never the choice and is skipped; its move log takes the leaders'
+// moves from the iteration it stopped being searched (entries that no
+// follower's fix-up writes).
 template <bool FLOAT>
 __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __restrict__ hdr,
                               const int32_t* __restrict__ fid, int L, int N, const int32_t* __restrict__ metric,
                               const uint8_t* __restrict__ cw, uint8_t* __restrict__ out_cw, int32_t* __restrict__ out_k,
-                              int32_t* __restrict__ out_metric, int T, int32_t* __restrict__ stats)
+                              int32_t* __restrict__ out_metric, int T, int32_t* __restrict__ stats,
+                              const int32_t* __restrict__ tag, int32_t* __restrict__ out_moves)
 {
     if (stats && blockIdx.x == 0) stats_add(hdr, T, stats);
     const int f2 = hdr[0];
     const int NB = N / 8;
     for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < f2; s += gridDim.x * blockDim.x) {
         const int f = fid[s];
+        uint32_t follower = 0;
+        if (tag)
+            for (int k = 0; k < L; ++k) {
+                const int tg = tag[(size_t)s * L + k];
+                if (tg >= 0) continue;
+                follower |= 1u << k;
+                if (!out_moves) continue;
+                int from = (-1 - tg) >> 5, cur = (-1 - tg) & 31;
+                for (int hop = 0; hop < L; ++hop) {
+                    const int ct = tag[(size_t)s * L + cur];
+                    const int upto = ct < 0 ? ((-1 - ct) >> 5) : T;
+                    for (int u = from; u < upto; ++u)
+                        out_moves[((size_t)f * L + k) * T + u] = out_moves[((size_t)f * L + cur) * T + u];
+                    if (ct >= 0) break;
+                    from = upto;
+                    cur = (-1 - ct) & 31;
+                }
+            }
         int kb = 0;
         int32_t mb = 0;
         if (FLOAT) {
             const float* y = (const float*)llr + (size_t)f * N;
             float best = 0.0f;
             for (int k = 0; k < L; ++k) {
+                if ((follower >> k) & 1) continue;
                 const uint8_t* c = cw + ((size_t)s * L + k) * NB;
                 float e = 0.0f;
                 for (int j = 0; j < N; ++j) {
@@ -1200,6 +1269,7 @@ __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __res
         } else {
             mb = metric[(size_t)s * L];
             for (int k = 1; k < L; ++k) {
+                if ((follower >> k) & 1) continue;
                 const int32_t v = metric[(size_t)s * L + k];
                 if (v < mb) { mb = v; kb = k; }
             }
@@ -1318,7 +1388,8 @@ void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
 {
     const int N = 1 << sg.m, KP = kpad(N);
     const bool fl = sg.dtype == MPWSD_F32;
-    hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(128), 0, s, w.hdr, 4 + T, zero_stats ? stats : nullptr, 2 + T);
+    hipLaunchKernelGGL(hdr_zero_kernel, dim3(1), dim3(128), 0, s, w.hdr, hdr_len(T), zero_stats ? stats : nullptr,
+                       2 + T);
     hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((sg.F + 255) / 256)), dim3(256), 0, s, sg.crc_ok, sg.F, w.hdr,
                        w.fid, w.slot);
     const int64_t work = sg.F * (int64_t)(L + 1) * (KP / 16);  // upper bound on the items' threads
@@ -1340,53 +1411,66 @@ int lanes_per_frame(int L)
     return lp;
 }
 
-// Resolve of iteration t; with merge (t < T - 1), the merge pass then builds
-// the next active list.
-void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, bool merge, hipStream_t s)
+// Resolve of iteration t: with merging, frame by frame (resolve_merge_kernel),
+// else column by column.
+template <bool FLOAT>
+void launch_resolve_merge(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, hipStream_t s)
 {
     const int N = 1 << sg.m, KP = kpad(N);
-    const int resolve_blocks = device_cus() * 4;
-    merge = merge && t + 1 < T;
-    int32_t* tag = merge ? w.tag : nullptr;
-    if (sg.dtype == MPWSD_F32)
-        hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves, N,
-                           sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (unsigned long long*)w.key64, w.fid,
-                           L, sg.out_moves, tag);
-    else
-        hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
-                           sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
-                           (long long*)w.key64, w.fid, L, sg.out_moves, tag);
-    if (!merge) return;
     const int lp = lanes_per_frame(L);
     const int64_t frames_per_block = 4 * (WAVE / lp);
     const unsigned blocks = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 4 * device_cus()));
-    const uint32_t* cw = (const uint32_t*)w.cw;
-    int32_t* out = w.act[(t + 1) & 1];
+        1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 2 * device_cus()));
+    const int32_t* fl_in = t == 0 ? nullptr : w.fl[t & 1];
+    int32_t* fl_out = w.fl[(t + 1) & 1];
+    int32_t* act_out = w.act[(t + 1) & 1];
+    unsigned long long* keys = (unsigned long long*)w.key64;
+    uint32_t* cw = (uint32_t*)w.cw;
+#define MPWSD_RESOLVE_MERGE(NW)                                                                                    \
+    hipLaunchKernelGGL((resolve_merge_kernel<FLOAT, NW>), dim3(blocks), dim3(256), 0, s, w.z, cw, w.metric,       \
+                       sg.moves, KP, sg.P, w.hdr, t, T, keys, w.fid, L, lp, sg.out_moves, w.tag, fl_in, fl_out,   \
+                       act_out)
     switch (N) {
-    case 32: hipLaunchKernelGGL(merge_kernel<1>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
-    case 64: hipLaunchKernelGGL(merge_kernel<2>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
-    case 128: hipLaunchKernelGGL(merge_kernel<4>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
-    default: hipLaunchKernelGGL(merge_kernel<8>, dim3(blocks), dim3(256), 0, s, w.hdr, t, L, lp, w.tag, cw, out); break;
+    case 32: MPWSD_RESOLVE_MERGE(1); break;
+    case 64: MPWSD_RESOLVE_MERGE(2); break;
+    case 128: MPWSD_RESOLVE_MERGE(4); break;
+    default: MPWSD_RESOLVE_MERGE(8); break;
     }
+#undef MPWSD_RESOLVE_MERGE
+}
+
+void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, bool merge, hipStream_t s)
+{
+    if (merge) {
+        if (sg.dtype == MPWSD_F32)
+            launch_resolve_merge<true>(sg, L, T, w, t, s);
+        else
+            launch_resolve_merge<false>(sg, L, T, w, t, s);
+        return;
+    }
+    const int N = 1 << sg.m, KP = kpad(N);
+    const int resolve_blocks = device_cus() * 4;
+    if (sg.dtype == MPWSD_F32)
+        hipLaunchKernelGGL(resolve_f32_kernel, dim3(resolve_blocks), dim3(256), 0, s, (float*)w.z, w.cw, sg.moves, N,
+                           sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T, (unsigned long long*)w.key64, w.fid,
+                           L, sg.out_moves);
+    else
+        hipLaunchKernelGGL(resolve_i8_kernel, dim3(resolve_blocks), dim3(256), 0, s, (int8_t*)w.z, w.cw, w.metric,
+                           sg.moves, N, KP, sg.P, w.act[t & 1], w.act[(t + 1) & 1], w.hdr, t, T,
+                           (long long*)w.key64, w.fid, L, sg.out_moves);
 }
 
 void seg_epilogue(const mpwsd_segment& sg, int L, int T, const SegWs& w, bool merge, int32_t* stats, hipStream_t s)
 {
     const int N = 1 << sg.m;
-    if (merge && T > 1) {
-        const int64_t cols = sg.F * (int64_t)L;
-        const unsigned fb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cols + 255) / 256, 4 * device_cus()));
-        hipLaunchKernelGGL(merge_finish_kernel, dim3(fb), dim3(256), 0, s, w.hdr, L, T, N / 8, w.tag, w.cw,
-                           sg.dtype == MPWSD_I8 ? w.metric : nullptr, w.fid, sg.out_moves);
-    }
+    const int32_t* tag = merge ? w.tag : nullptr;
     const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((sg.F + 255) / 256, 4096));
     if (sg.dtype == MPWSD_F32)
         hipLaunchKernelGGL(select_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N, w.metric,
-                           w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats);
+                           w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats, tag, sg.out_moves);
     else
         hipLaunchKernelGGL(select_kernel<false>, dim3(blocks), dim3(256), 0, s, sg.llr, w.hdr, w.fid, L, N,
-                           w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats);
+                           w.metric, w.cw, sg.out_cw, sg.out_k, sg.out_metric, T, stats, tag, sg.out_moves);
 }
 
 int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* stats, bool zero_stats,
@@ -1400,7 +1484,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
             launch_search_f32(w, sg, t, s, device_cus() * 4);
         else
             mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, sg.grouped, sg.grouped_chunks,
-                                    w.act[t & 1], w.hdr + 2 + t, (long long*)w.key64, variant[t], blocks_per_cu[t], s);
+                                    w.act[t & 1], w.hdr + ncol(t), (long long*)w.key64, variant[t], blocks_per_cu[t],
+                                    s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         seg_resolve(sg, L, T, w, t, merge, s);
     }
@@ -1434,7 +1519,7 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         for (int i = 0, j = 0; i < nseg; ++i) {
             if (segs[i].F == 0) continue;
             ms.s[j].act = w[i].act[t & 1];
-            ms.s[j].count = w[i].hdr + 2 + t;
+            ms.s[j].count = w[i].hdr + ncol(t);
             ++j;
         }
         if (ev) (void)hipEventRecord(ev[2 * t], s);
