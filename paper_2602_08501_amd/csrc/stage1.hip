@@ -64,12 +64,12 @@ __device__ inline uint32_t pk_max_i16(uint32_t a, uint32_t b)
     return as_u(x > y ? x : y);
 }
 __device__ inline uint32_t pk_abs_i16(uint32_t a) { return pk_max_i16(a, pk_sub_u16(0u, a)); }
-// min-sum f on both halves: sgn(a) sgn(b) min(|a|, |b|)
+// min-sum f on both halves: sgn(a) sgn(b) min(|a|, |b|), which for integers
+// equals max(min(a, b), -max(a, b)) (same signs: the smaller magnitude with
+// their sign; opposite signs: minus the smaller magnitude; 0 when a or b is 0)
 __device__ inline uint32_t f_pk(uint32_t a, uint32_t b)
 {
-    const uint32_t sg = pk_ashr15(a ^ b);
-    const uint32_t mn = pk_min_i16(pk_abs_i16(a), pk_abs_i16(b));
-    return pk_sub_u16(mn ^ sg, sg);
+    return pk_max_i16(pk_min_i16(a, b), pk_sub_u16(0u, pk_max_i16(a, b)));
 }
 // g on both halves: b + (1 - 2 v) a, v = bit 0 (low half) / bit 1 (high half)
 __device__ inline uint32_t g_pk(uint32_t a, uint32_t b, uint32_t bits2)
@@ -116,10 +116,11 @@ constexpr int KIND_R0 = 1, KIND_REP = 2;
 template <int X>
 __device__ inline uint32_t xor_lane(uint32_t v)
 {
+    // (quad permutes read a valid lane for every lane, so no old value is kept)
     if constexpr (X == 1)
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
     else if constexpr (X == 2)
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
     else
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));
 }
@@ -458,6 +459,51 @@ template <int M, int L, bool FLOAT> struct Scl {
         }
     }
     __device__ static uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) { return max(min(a, b), min(max(a, b), c)); }
+
+    // One 32-bit key per lane over the frame's L lanes: a bitonic sort into
+    // descending order (stages numbered 0 .. NSORT1 - 1), then the ascending
+    // bitonic merge of a bitonic sequence (stages NSORT1 ...).  Bit P of fd
+    // set: stage P keeps the larger key in this lane.
+    static constexpr int NSORT1 = lg2(L) * (lg2(L) + 1) / 2;
+    template <int KS, int J, int P>
+    __device__ static uint32_t sort1_dirs(int s)
+    {
+        if constexpr (KS <= L) {
+            const uint32_t bit = ((((s & J) == 0) == ((s & KS) == 0)) ? 1u : 0u) << P;
+            if constexpr (J > 1) return bit | sort1_dirs<KS, J / 2, P + 1>(s);
+            else return bit | sort1_dirs<KS * 2, KS, P + 1>(s);
+        } else {
+            return 0u;
+        }
+    }
+    template <int J, int P>
+    __device__ static uint32_t merge1_dirs(int s)
+    {
+        if constexpr (J >= 1) return ((((s & J) != 0) ? 1u : 0u) << P) | merge1_dirs<J / 2, P + 1>(s);
+        else return 0u;
+    }
+    __device__ static uint32_t one_key_dirs(int s) { return sort1_dirs<2, 1, 0>(s) | merge1_dirs<L / 2, NSORT1>(s); }
+    template <int KS, int J, int P>
+    __device__ static uint32_t sort1(uint32_t x, uint32_t fd)
+    {
+        if constexpr (KS <= L) {
+            x = med3u(x, xor_lane<J>(x), (uint32_t)(-(int32_t)((fd >> P) & 1u)));
+            if constexpr (J > 1) return sort1<KS, J / 2, P + 1>(x, fd);
+            else return sort1<KS * 2, KS, P + 1>(x, fd);
+        } else {
+            return x;
+        }
+    }
+    template <int J, int P>
+    __device__ static uint32_t merge1(uint32_t x, uint32_t fd)
+    {
+        if constexpr (J >= 1) {
+            x = med3u(x, xor_lane<J>(x), (uint32_t)(-(int32_t)((fd >> P) & 1u)));
+            return merge1<J / 2, P + 1>(x, fd);
+        } else {
+            return x;
+        }
+    }
     template <int KS, int J>
     __device__ static void stage(Key& x0, Key& x1, int s, uint32_t dirs)
     {
@@ -523,6 +569,10 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     bool valid = (slot == 0);
     uint64_t ptrs = 0;  // byte l: group slot owning this path's level-l buffer
     const uint32_t dirs = K::template bitonic_dirs<2>(slot);  // sorting-network directions of this lane
+    const uint32_t fdirs = FLOAT ? 0u : K::one_key_dirs(slot);
+    // the slots hold the paths in ascending (PM, index) order; a frozen leaf
+    // adds penalties path by path and breaks that order until the next sort
+    bool sorted = true;
     uint32_t ub[NW];
 #pragma unroll
     for (int i = 0; i < NW; ++i) ub[i] = 0;
@@ -543,18 +593,35 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
         const bool frozen = kind == KIND_R0 || (kind == 0 && ((info[last >> 6] >> (last & 63)) & 1ull) == 0);
         if (frozen) {
             if (valid) pm = pm + d0;
+            sorted = false;
             continue;  // u = 0 already
         }
-        // information bit: the 2L children sorted by (PM, parent slot, bit)
-        // with a bitonic network over the frame's L lanes (two keys per lane,
-        // partners reached through DPP / swizzles); slot s takes the s-th key,
-        // which also names its parent slot and bit
-        Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
-        Key x1 = K::make_key(valid, (V)(pm + d1), 2 * slot + 1);
-        K::template bitonic<2>(x0, x1, slot, dirs);
-        const int src = gbase + (slot >> 1);
-        const Key y0 = shfl_key(x0, src), y1 = shfl_key(x1, src);
-        const Key mine = (slot & 1) ? y1 : y0;
+        // information bit: slot s takes the s-th smallest of the 2L children's
+        // keys (PM, parent slot, bit), which also names its parent and bit
+        Key mine;
+        bool fast = false;
+        if constexpr (!FLOAT) fast = kind == 0 && sorted;
+        if (fast) {
+            // ordinary leaf: one child of each path adds nothing to its PM, so
+            // those L keys are already ascending by slot; the other L (the
+            // penalised children) are sorted descending, the lane-wise minimum
+            // of the two holds the L smallest as a bitonic sequence, and one
+            // bitonic merge puts the s-th smallest on slot s
+            const int zb = lam < 0 ? 1 : 0;
+            const Key a = K::make_key(valid, pm, 2 * slot + zb);
+            const Key b = K::make_key(valid, (V)(pm + (lam < 0 ? -lam : lam)), 2 * slot + 1 - zb);
+            const Key bd = (Key)K::template sort1<2, 1, 0>((uint32_t)b, fdirs);
+            mine = (Key)K::template merge1<L / 2, K::NSORT1>((uint32_t)(a < bd ? a : bd), fdirs);
+        } else {
+            // all 2L children (two keys per lane) through a bitonic sort
+            Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
+            Key x1 = K::make_key(valid, (V)(pm + d1), 2 * slot + 1);
+            K::template bitonic<2>(x0, x1, slot, dirs);
+            const int src = gbase + (slot >> 1);
+            const Key y0 = shfl_key(x0, src), y1 = shfl_key(x1, src);
+            mine = (slot & 1) ? y1 : y0;
+        }
+        sorted = true;
         const int c = K::key_index(mine);
         valid = K::key_valid(mine);
         pm = K::key_pm(mine);
