@@ -116,13 +116,21 @@ constexpr int KIND_R0 = 1, KIND_REP = 2;
 template <int X>
 __device__ inline uint32_t xor_lane(uint32_t v)
 {
-    // (quad permutes read a valid lane for every lane, so no old value is kept)
-    if constexpr (X == 1)
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
-    else if constexpr (X == 2)
-        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
-    else
+    // (every lane reads a lane of its own 16-lane row, so no old value is kept)
+    if constexpr (X == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (X == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (X == 4) {
+        // lanes with bit 2 clear read 4 lanes up (row_shl:4), the others 4 down (row_shr:4)
+        const uint32_t up = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x104, 0xF, 0xF, false);
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x114, 0xF, 0xF, false);
+        return (threadIdx.x & 4) ? dn : up;
+    } else if constexpr (X == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else {
         return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (X << 10));
+    }
 }
 template <int X> __device__ inline uint32_t xor_key(uint32_t v) { return xor_lane<X>(v); }
 template <int X> __device__ inline uint64_t xor_key(uint64_t v)
