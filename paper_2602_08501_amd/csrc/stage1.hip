@@ -587,9 +587,16 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
 #pragma unroll
     for (int l = 0; l < M; ++l) ptrs |= (uint64_t)slot << (8 * l);
 
+    // the schedule is read with scalar loads from the kernel arguments, each
+    // entry one node ahead of its use
+    const __attribute__((address_space(4))) uint32_t* sw =
+        (const __attribute__((address_space(4))) uint32_t*)(const void*)sched.v;
+    auto sched_at = [&](int j) { return (int)((sw[j >> 2] >> (8 * (j & 3))) & 0xFFu); };
+    int e_next = FLOAT ? 0 : sched_at(0);
     for (int i = 0; i < N;) {
-        const int e = FLOAT ? 0 : sched.v[i];
+        const int e = e_next;
         const int lev = e & 15, kind = e >> 4;
+        if (!FLOAT && i + (1 << lev) < N) e_next = sched_at(i + (1 << lev));
         V d0, d1;
         const V lam = K::node(sm, lane, gbase, i, lev, slot, ptrs, ub, d0, d1);
         const int last = i + (1 << lev) - 1;  // the leaf a decision is taken at
