@@ -354,9 +354,12 @@ int mpwsd_graph_destroy(mpwsd_graph* graph);
  *      ticks as well;
  *   3. runs ONE stage-2 iteration (search + apply) over the whole pool: new
  *      and old paths share the same launches;
- *   4. completes every frame whose L paths have all stopped (no improving
- *      move, or T accepted moves), with the same choice rule as
- *      mpwsd_decode_batch, and frees its slot once the host has read it.
+ *   4. merges paths of a frame that reach the same centre, as
+ *      mpwsd_decode_batch does, and completes every frame with no path left
+ *      to search (each stopped: no improving move, T accepted moves, or at
+ *      the centre of a path that stopped; or follows a path of smaller
+ *      index), with the same choice rule as mpwsd_decode_batch, and frees
+ *      its slot once the host has read it.
  * A frame's result therefore does not depend on which other frames share
  * its ticks: it equals mpwsd_decode_batch's result for that frame alone.
  * Ticks run asynchronously on the server's stream; up to two are in flight.

@@ -8,11 +8,15 @@
 //   -> stage 1 (mpwsd_stage1_scl on the contiguous new frames)
 //   -> enter: decided frames emit a result record, the others' paths join
 //      the active list that already holds older paths
-//   -> one search over the whole active list -> resolve: apply moves; paths
-//      that stop (no improving move or T moves) count down their frame, and
-//      the last one to stop chooses the frame's decision and emits a record
+//   -> one search over the whole active list -> resolve, frame by frame:
+//      apply moves; a path that moved onto the centre of a path of its frame
+//      that does not go on stops, one that moved onto the centre of a moving
+//      path of smaller index follows it (equal centres have the same future,
+//      and the follower can never be the frame's choice); when no path of a
+//      frame goes on, the frame's decision is chosen and a record emitted
 //   -> D2H of the result records.
-// Paths that move and have iterations left form the next tick's list.
+// Paths that move, have iterations left and were not merged form the next
+// tick's list, and their frames the next frame list.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +39,11 @@ struct Record {
     uint8_t cw[32];
 };
 
-enum { H_CNT0 = 0, H_CNT1 = 1, H_CCOUNT = 2, H_ERR = 3, H_WORDS = 64 };
+// header words: records, errors, and per active list (two, ping-pong) the
+// pair (columns, frames), 8-byte aligned so that one 64-bit atomic appends
+// columns and frames together
+enum { H_CCOUNT = 2, H_ERR = 3, H_LIST0 = 4, H_LIST1 = 6, H_WORDS = 64 };
+__host__ __device__ inline int list_words(int which) { return which ? H_LIST1 : H_LIST0; }
 
 // Position of this lane's item in a list appended to by the whole wave (one
 // atomic per wave).  Every lane of the wave must call it.
@@ -52,7 +60,8 @@ __device__ inline int wave_append(bool flag, int32_t* counter)
 __global__ void srv_prep_kernel(int32_t* hdr, int nxt)
 {
     if (threadIdx.x == 0) {
-        hdr[nxt ? H_CNT1 : H_CNT0] = 0;
+        hdr[list_words(nxt)] = 0;
+        hdr[list_words(nxt) + 1] = 0;
         hdr[H_CCOUNT] = 0;
     }
 }
@@ -79,7 +88,7 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
     int n, int L, int N, int KP, const int8_t* __restrict__ q, const uint8_t* __restrict__ anc,
     const uint8_t* __restrict__ ok, const int32_t* __restrict__ newslot, uint8_t* __restrict__ cw,
     int8_t* __restrict__ zneg, int32_t* __restrict__ metric, int32_t* __restrict__ citer, long long* __restrict__ key,
-    int32_t* __restrict__ fdone, int32_t* __restrict__ act, int32_t* __restrict__ hdr, int cur,
+    int32_t* __restrict__ tag, int32_t* __restrict__ act, int32_t* __restrict__ fl, int32_t* __restrict__ hdr, int cur,
     Record* __restrict__ rec)
 {
     const int NB = N / 8;
@@ -120,69 +129,106 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
             metric[col] = m;
             citer[col] = 0;
             key[col] = LLONG_MAX;
-            if (k == 0) fdone[slot] = 0;
+            tag[col] = 1;
         }
-        const int apos = wave_append(join, &hdr[cur ? H_CNT1 : H_CNT0]);
+        const int apos = wave_append(join, &hdr[list_words(cur)]);
         if (join) act[apos] = col;
+        const int fpos = wave_append(join && k == 0, &hdr[list_words(cur) + 1]);
+        if (join && k == 0) fl[fpos] = slot;
     }
 }
 
-// thread per active column
+// Frame by frame (L lanes per frame, L a power of two <= 32), over the
+// frames that hold a searched path.  tag[column]: 1 searched this tick, 0
+// stopped (final state), < 0 following another path of the frame.
 __global__ __launch_bounds__(256) void srv_resolve_kernel(
     int L, int T, int N, int KP, int64_t P, const uint8_t* __restrict__ moves, uint8_t* __restrict__ cw,
     int8_t* __restrict__ zneg, int32_t* __restrict__ metric, int32_t* __restrict__ citer, long long* __restrict__ key,
-    int32_t* __restrict__ fdone, const int32_t* __restrict__ act_in, int32_t* __restrict__ act_out,
-    int32_t* __restrict__ hdr, int cur, Record* __restrict__ rec)
+    int32_t* __restrict__ tag, const int32_t* __restrict__ fl_in, int32_t* __restrict__ fl_out,
+    int32_t* __restrict__ act_out, int32_t* __restrict__ hdr, int cur, Record* __restrict__ rec)
 {
-    const int NB = N / 8;
-    const int n = hdr[cur ? H_CNT1 : H_CNT0];
-    int32_t* cnt_out = &hdr[cur ? H_CNT0 : H_CNT1];
-    for (int base = blockIdx.x * blockDim.x + (threadIdx.x & ~63); base < n; base += gridDim.x * blockDim.x) {
-        const int pos = base + (threadIdx.x & 63);
-        bool cont = false, fin = false;
-        int col = 0;
-        if (pos < n) {
-            col = act_in[pos];
+    const int NB = N / 8, NW = N / 32;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per_wave = 64 / L;
+    const int g = lane / L, k = lane % L, gbase = g * L;
+    const uint64_t gmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << gbase;
+    const int nfr = hdr[list_words(cur) + 1];
+    const int step = gridDim.x * (blockDim.x / 64) * per_wave;
+    for (int i0 = (blockIdx.x * (blockDim.x / 64) + wave) * per_wave; i0 < nfr; i0 += step) {
+        const int i = i0 + g;
+        const bool ok = i < nfr;
+        const int slot = ok ? fl_in[i] : 0;
+        const int col = slot * L + k;
+        const int tg = ok ? tag[col] : -1;
+        bool moved = false, cont = false;
+        if (tg == 1) {
             const long long kv = key[col];
             key[col] = LLONG_MAX;
             const int S = (int)(kv >> 32);
             const int64_t p = (int64_t)(uint32_t)kv;
-            const bool moved = kv != LLONG_MAX && S < 0 && p < P;
+            moved = kv != LLONG_MAX && S < 0 && p < P;
             if (moved) {
                 mpwsd::apply_move_i8(moves + (size_t)p * NB, cw + (size_t)col * NB, zneg + (size_t)col * KP, N);
                 metric[col] += S;
                 citer[col] += 1;
             }
             cont = moved && citer[col] < T;
-            fin = !cont;
         }
-        const int apos = wave_append(cont, cnt_out);
-        if (cont) act_out[apos] = col;
-        bool emit = false;
-        int slot = 0, kb = 0, mb = 0;
-        if (fin) {
-            slot = col / L;
-            __threadfence();
-            if (atomicAdd(&fdone[slot], 1) == L - 1) {
-                __threadfence();
-                // every path of this frame has stopped: the choice of Alg. 1
-                mb = metric[(size_t)slot * L];
-                for (int k = 1; k < L; ++k) {
-                    const int v = metric[(size_t)slot * L + k];
-                    if (v < mb) { mb = v; kb = k; }
+        // this lane's centre and metric (its own writes above)
+        uint32_t c[8] = {};
+        if (tg >= 0)
+            for (int w = 0; w < NW; ++w) c[w] = reinterpret_cast<const uint32_t*>(cw)[(size_t)col * NW + w];
+        const int mv = tg >= 0 ? metric[col] : INT_MAX;
+        // merging: paths of the same frame share every tick, so a path that
+        // goes on is compared with the paths that do not (their centres have
+        // no improving move) and with the other paths that go on
+        const uint64_t cb = __ballot(cont);
+        bool stop = false;
+        int lead = -1;
+        if (cb) {
+            const uint64_t sb = __ballot(tg >= 0 && !cont);
+            for (int j = 0; j < L; ++j) {
+                bool eq = true;
+                for (int w = 0; w < 8; ++w)
+                    if (w < NW) eq = (__shfl(c[w], gbase + j) == c[w]) && eq;
+                if (cont && eq && j != k) {
+                    if ((sb >> (gbase + j)) & 1) stop = true;
+                    else if (((cb >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
                 }
-                emit = true;
             }
         }
+        const bool keep = cont && !stop && lead < 0;
+        if (tg == 1) tag[col] = keep ? 1 : ((cont && !stop) ? -1 - lead : 0);
+        // next column and frame lists: one 64-bit atomic per wave
+        const uint64_t kb = __ballot(keep);
+        const uint64_t fb = __ballot(k == 0 && ok && ((kb & gmask) != 0));
+        unsigned long long base = 0;
+        if (lane == 0 && kb)
+            base = atomicAdd(reinterpret_cast<unsigned long long*>(hdr + list_words(cur ^ 1)),
+                             ((unsigned long long)__popcll(fb) << 32) | (unsigned long long)__popcll(kb));
+        base = __shfl(base, 0);
+        if (keep) act_out[(int)(uint32_t)base + __popcll(kb & ((1ull << lane) - 1ull))] = col;
+        if ((fb >> lane) & 1) fl_out[(int)(base >> 32) + __popcll(fb & ((1ull << lane) - 1ull))] = slot;
+        // a frame with no path left to search takes the smallest metric among
+        // its non-following paths, ties to the smallest index (Alg. 1)
+        const bool done = ok && (kb & gmask) == 0;
+        int kbst = 0, mb = INT_MAX;
+        for (int j = 0; j < L; ++j) {
+            const int v = __shfl(mv, gbase + j);
+            if (v < mb) { mb = v; kbst = j; }
+        }
+        uint32_t cc[8] = {};
+        for (int w = 0; w < 8; ++w)
+            if (w < NW) cc[w] = __shfl(c[w], gbase + kbst);
+        const bool emit = done && k == 0;
         const int rpos = wave_append(emit, &hdr[H_CCOUNT]);
         if (emit) {
             Record& r = rec[rpos];
             r.slot = slot;
             r.stage = 2;
-            r.k = kb;
+            r.k = kbst;
             r.metric = mb;
-            const uint8_t* c = cw + ((size_t)slot * L + kb) * NB;
-            for (int b = 0; b < 32; ++b) r.cw[b] = b < NB ? c[b] : 0;
+            for (int b = 0; b < 32; ++b) r.cw[b] = b < NB ? (uint8_t)(cc[b >> 2] >> (8 * (b & 3))) : 0;
         }
     }
 }
@@ -190,7 +236,8 @@ __global__ __launch_bounds__(256) void srv_resolve_kernel(
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct CodeLayout {
-    size_t yst, sst, qst, ancst, okst, newslot, cw, zneg, metric, citer, key, fdone, act0, act1, hdr, rec, bytes;
+    size_t yst, sst, qst, ancst, okst, newslot, cw, zneg, metric, citer, key, tag, fl0, fl1, act0, act1, hdr, rec,
+        bytes;
 };
 
 CodeLayout layout(const mpwsd_server_code& c)
@@ -210,7 +257,9 @@ CodeLayout layout(const mpwsd_server_code& c)
     l.metric = take(C * L * 4);
     l.citer = take(C * L * 4);
     l.key = take(C * L * 8);
-    l.fdone = take(C * 4);
+    l.tag = take(C * L * 4);
+    l.fl0 = take(C * 4);
+    l.fl1 = take(C * 4);
     l.act0 = take(C * L * 4);
     l.act1 = take(C * L * 4);
     l.hdr = take(H_WORDS * 4);
@@ -353,6 +402,7 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
         const int L = c.c.L, nxt = c.cur ^ 1;
         int32_t* hdr = c.at<int32_t>(c.lay.hdr);
         int32_t* act[2] = {c.at<int32_t>(c.lay.act0), c.at<int32_t>(c.lay.act1)};
+        int32_t* fl[2] = {c.at<int32_t>(c.lay.fl0), c.at<int32_t>(c.lay.fl1)};
         hipLaunchKernelGGL(srv_prep_kernel, dim3(1), dim3(64), 0, st, hdr, nxt);
         if (n_new > 0) {
             (void)hipMemcpyAsync(c.at<float>(c.lay.yst), p.y, sizeof(float) * c.N * n_new, hipMemcpyHostToDevice, st);
@@ -371,18 +421,19 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
                                dim3(256), 0, st, n_new, L, c.N, c.KP, c.at<int8_t>(c.lay.qst),
                                c.at<uint8_t>(c.lay.ancst), c.at<uint8_t>(c.lay.okst), c.at<int32_t>(c.lay.newslot),
                                c.at<uint8_t>(c.lay.cw), c.at<int8_t>(c.lay.zneg), c.at<int32_t>(c.lay.metric),
-                               c.at<int32_t>(c.lay.citer), c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.fdone),
-                               act[c.cur], hdr, c.cur, c.at<Record>(c.lay.rec));
+                               c.at<int32_t>(c.lay.citer), c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.tag),
+                               act[c.cur], fl[c.cur], hdr, c.cur, c.at<Record>(c.lay.rec));
         }
         // one stage-2 iteration over every active path of this code
         mpwsd::launch_search_i8(c.N, c.at<int8_t>(c.lay.zneg), c.c.moves, c.c.P, c.c.grouped, c.c.grouped_chunks,
-                                act[c.cur], hdr + (c.cur ? H_CNT1 : H_CNT0), c.at<long long>(c.lay.key), -1, 0, st);
-        const int cols = c.c.capacity * L;
-        hipLaunchKernelGGL(srv_resolve_kernel, dim3((unsigned)std::min(((cols + 255) / 256), 2048)), dim3(256), 0,
-                           st, L, c.c.T, c.N, c.KP, c.c.P, c.c.moves, c.at<uint8_t>(c.lay.cw),
+                                act[c.cur], hdr + list_words(c.cur), c.at<long long>(c.lay.key), -1, 0, st);
+        const int frames_per_block = 4 * (64 / L);
+        hipLaunchKernelGGL(srv_resolve_kernel,
+                           dim3((unsigned)std::min((c.c.capacity + frames_per_block - 1) / frames_per_block, 2048)),
+                           dim3(256), 0, st, L, c.c.T, c.N, c.KP, c.c.P, c.c.moves, c.at<uint8_t>(c.lay.cw),
                            c.at<int8_t>(c.lay.zneg), c.at<int32_t>(c.lay.metric), c.at<int32_t>(c.lay.citer),
-                           c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.fdone), act[c.cur], act[nxt], hdr, c.cur,
-                           c.at<Record>(c.lay.rec));
+                           c.at<long long>(c.lay.key), c.at<int32_t>(c.lay.tag), fl[c.cur], fl[nxt], act[nxt], hdr,
+                           c.cur, c.at<Record>(c.lay.rec));
         (void)hipMemcpyAsync(p.hdr, hdr, sizeof(int32_t) * H_WORDS, hipMemcpyDeviceToHost, st);
         (void)hipMemcpyAsync(p.rec, c.at<Record>(c.lay.rec), sizeof(Record) * p.maxrec, hipMemcpyDeviceToHost, st);
         c.cur = nxt;
