@@ -680,19 +680,33 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     }
 }
 
+__device__ inline uint32_t quantize1(float v, float s, int32_t* __restrict__ bad)
+{
+    if (!isfinite(v)) {
+        if (bad) atomicAdd(bad, 1);
+        return 0u;
+    }
+    float t = rintf(__fmul_rn(v, s));  // a product overflowing to +-inf clamps below
+    t = fminf(fmaxf(t, -127.0f), 127.0f);
+    return (uint32_t)(uint8_t)(int8_t)t;
+}
+
 __global__ void quantize_kernel(const float* __restrict__ y, int64_t n, float s, int8_t* __restrict__ q,
                                 int32_t* __restrict__ bad)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const float v = y[i];
-        if (!isfinite(v)) {
-            q[i] = 0;
-            if (bad) atomicAdd(bad, 1);
-            continue;
-        }
-        float t = rintf(__fmul_rn(v, s));  // a product overflowing to +-inf clamps below
-        t = fminf(fmaxf(t, -127.0f), 127.0f);
-        q[i] = (int8_t)t;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        q[i] = (int8_t)quantize1(y[i], s, bad);
+}
+
+// four values per thread: one 16-byte load, one 4-byte store (y 16-byte and
+// q 4-byte aligned; n4 = number of quadruples)
+__global__ void quantize4_kernel(const float4* __restrict__ y, int64_t n4, float s, uint32_t* __restrict__ q,
+                                 int32_t* __restrict__ bad)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 v = y[i];
+        q[i] = quantize1(v.x, s, bad) | (quantize1(v.y, s, bad) << 8) | (quantize1(v.z, s, bad) << 16) |
+               (quantize1(v.w, s, bad) << 24);
     }
 }
 
@@ -756,9 +770,20 @@ extern "C" int mpwsd_quantize_llr(const float* y, int64_t n, float scale, int8_t
     if (n < 0 || (n > 0 && (!y || !q))) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_quantize_llr: bad arguments");
     if (!std::isfinite(scale)) return mpwsd::fail(MPWSD_ERR_ARG, "mpwsd_quantize_llr: scale must be finite");
     if (n == 0) return MPWSD_OK;
-    const int64_t want = (n + 255) / 256;
-    const unsigned blocks = (unsigned)(want < 8192 ? want : 8192);
-    hipLaunchKernelGGL(quantize_kernel, dim3(blocks), dim3(256), 0, stream, y, n, scale, q, bad);
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(y) & 15u) == 0 && (reinterpret_cast<uintptr_t>(q) & 3u) == 0 && n >= 4) {
+        const int64_t n4 = n / 4;
+        const int64_t want4 = (n4 + 255) / 256;
+        hipLaunchKernelGGL(quantize4_kernel, dim3((unsigned)(want4 < 8192 ? want4 : 8192)), dim3(256), 0, stream,
+                           reinterpret_cast<const float4*>(y), n4, scale, reinterpret_cast<uint32_t*>(q), bad);
+        done = 4 * n4;
+    }
+    if (done < n) {
+        const int64_t rest = n - done;
+        const int64_t want = (rest + 255) / 256;
+        hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)(want < 8192 ? want : 8192)), dim3(256), 0, stream,
+                           y + done, rest, scale, q + done, bad);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_quantize_llr: %s", hipGetErrorString(e));
     return MPWSD_OK;

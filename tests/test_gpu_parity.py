@@ -75,6 +75,14 @@ def test_quantizer_parity_and_nonfinite():
     y2[[7, 11, 13]] = [np.nan, np.inf, -np.inf]
     q2 = D.quantize(torch.from_numpy(y2).to(DEV), s, bad).cpu().numpy()
     assert bad.item() == 3 and q2[7] == q2[11] == q2[13] == 0
+    # unaligned input and output (one value in): the same values element by element
+    yd = torch.from_numpy(y2).to(DEV)
+    bad.zero_()
+    q3 = D.quantize(yd[1:], s, bad).cpu().numpy()
+    assert np.array_equal(q3, q2[1:]) and bad.item() == 3
+    out = torch.zeros(len(y2) + 1, dtype=torch.int8, device=DEV)
+    D.quantize(yd, s, bad, out=out[1:])
+    assert np.array_equal(out[1:].cpu().numpy(), q2)
 
 
 # ---------------------------------------------------------------- stage 1
