@@ -88,7 +88,7 @@ def test_grouped_equals_plain_every_variant(wl, L, T, F):
     ref, st_ref = decode(code(wl.r, wl.m, False), q, anchors, L, T)
     assert st_ref[1] == F * L and st_ref[2] > 0  # every path searched, some still moving
     cd = code(wl.r, wl.m, True)
-    for variant in range(5):
+    for variant in range(len(D._lib.mpwsd_search_variants())):
         for bpc in (0, 1):
             got, st = decode(cd, q, anchors, L, T, variant, bpc)
             for key in ref:
