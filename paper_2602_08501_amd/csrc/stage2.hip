@@ -22,8 +22,8 @@
 // which is order independent, so the result does not depend on the split.
 // After each search a resolve pass applies the moves, logs them and builds
 // the next iteration's active list (a column that did not move can never
-// move again); a merge pass drops the columns whose centre another column of
-// the frame already holds.  All counts live in device memory, so T
+// move again); with merging it also drops the columns whose centre another
+// column of the frame already holds.  All counts live in device memory, so T
 // iterations enqueue without any host round trip and can be captured in a
 // HIP graph.
 #include <hip/hip_runtime.h>
