@@ -4,9 +4,10 @@
 // runs on every frame (always-on mode, Sec. III-C).
 //
 // One wavefront per frame (workgroup of 64 lanes):
-//   1. reliability order: every position's rank is the number of positions
-//      with a smaller key (|llr| descending, then position), counted against
-//      all keys in LDS; position j is written to slot rank(j);
+//   1. reliability order by the key (|llr| descending, then position): int8
+//      keys fit 16 bits and are sorted in registers by a bitonic network; a
+//      binary32 position's rank is the number of positions with a smaller
+//      key, counted against all keys in LDS; position j goes to slot rank(j);
 //   2. most reliable basis: lane i holds generator row i (row A[i] of
 //      F^{(x)m}, bit-packed).  Positions are visited in reliability order;
 //      a ballot finds the unpivoted rows with a 1 there, the lowest such
@@ -105,6 +106,39 @@ __device__ inline uint64_t wave_xor_u64(uint64_t v)
     return readlane_u64(v, 0) ^ readlane_u64(v, 16) ^ readlane_u64(v, 32) ^ readlane_u64(v, 48);
 }
 
+// Ascending bitonic sort of the 64 E keys of a wave, E per lane (element
+// lane * E + h in x[h]): partners closer than E in registers, the others by
+// lane exchanges.
+template <int E>
+__device__ inline void wave_sort(uint32_t (&x)[E], int lane)
+{
+    constexpr int M = WAVE * E;
+#pragma unroll
+    for (int ks = 2; ks <= M; ks <<= 1) {
+#pragma unroll
+        for (int j = ks >> 1; j > 0; j >>= 1) {
+            if (j < E) {
+#pragma unroll
+                for (int h = 0; h < E; ++h) {
+                    if (h & j) continue;
+                    const bool up = ((lane * E + h) & ks) == 0;
+                    const uint32_t lo = min(x[h], x[h | j]), hi = max(x[h], x[h | j]);
+                    x[h] = up ? lo : hi;
+                    x[h | j] = up ? hi : lo;
+                }
+            } else {
+#pragma unroll
+                for (int h = 0; h < E; ++h) {
+                    const uint32_t y = (uint32_t)__shfl_xor((int)x[h], j / E);
+                    const int e = lane * E + h;
+                    const bool keep_min = ((e & j) == 0) == ((e & ks) == 0);
+                    x[h] = keep_min ? min(x[h], y) : max(x[h], y);
+                }
+            }
+        }
+    }
+}
+
 // Pattern e = {e_0 < e_1 < ...} of size s (s <= 4), one byte per element.
 struct Pattern {
     int s;
@@ -179,7 +213,7 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
 
     __shared__ float ys[FLOAT ? MAXN : 1];
     __shared__ int8_t qs[MAXN];
-    __shared__ uint64_t keys[MAXN];
+    __shared__ uint64_t keys[FLOAT ? MAXN : 1];  // reliability keys (binary32 form)
     __shared__ uint16_t sorted[MAXN];
     __shared__ uint16_t info[MAXK];
     __shared__ uint16_t mrb[MAXK];
@@ -201,14 +235,34 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
             qs[j] = v;
             mag = (uint32_t)(v < 0 ? -(int)v : (int)v);
         }
-        keys[j] = ((uint64_t)(0xFFFFFFFFu - mag) << 32) | (uint32_t)j;
+        if (FLOAT) keys[j] = ((uint64_t)(0xFFFFFFFFu - mag) << 32) | (uint32_t)j;
     }
-    __syncthreads();
-    for (int j = lane; j < N; j += WAVE) {
-        const uint64_t kj = keys[j];
-        int rank = 0;
-        for (int i = 0; i < N; ++i) rank += keys[i] < kj;
-        sorted[rank] = (uint16_t)j;
+    if (FLOAT) {
+        __syncthreads();
+        for (int j = lane; j < N; j += WAVE) {
+            const uint64_t kj = keys[j];
+            int rank = 0;
+            for (int i = 0; i < N; ++i) rank += keys[i] < kj;
+            sorted[rank] = (uint16_t)j;
+        }
+    } else {
+        // 16-bit keys (255 - |q|, position), unique: sorted in registers
+        // (positions past N take the largest key and sort last)
+        uint32_t x[W];
+#pragma unroll
+        for (int h = 0; h < W; ++h) {
+            const int e = lane * W + h;
+            uint32_t key = 0xFFFFu;
+            if (e < N) {
+                const int v = ((const int8_t*)llr)[f * N + e];
+                key = ((255u - (uint32_t)(v < 0 ? -v : v)) << 8) | (uint32_t)e;
+            }
+            x[h] = key;
+        }
+        wave_sort<W>(x, lane);
+#pragma unroll
+        for (int h = 0; h < W; ++h)
+            if (lane * W + h < N) sorted[lane * W + h] = (uint16_t)(x[h] & 0xFFu);
     }
     // information set A = {i : popcount(i) >= m - r}, ascending (compaction by ballot)
     {
