@@ -157,16 +157,24 @@ __device__ inline Pattern unrank(uint32_t num, int K)
         ++s;
     }
     p.s = s;
+    // element t is the largest x whose patterns starting below it number at
+    // most num: those are sum_{x' = a}^{x - 1} C(K-1-x', r) = C(K-a, r+1) -
+    // C(K-x, r+1) (a = first allowed value, r = elements after t), found by
+    // bisection on the decreasing C(K-x, r+1)
     int x = 0;
     for (int t = 0; t < s; ++t) {
-        for (;;) {
-            const uint32_t cnt = binom_small(K - 1 - x, s - 1 - t);
-            if (num < cnt) break;
-            num -= cnt;
-            ++x;
+        const int r = s - 1 - t;
+        const uint32_t tot = binom_small(K - x, r + 1);
+        const uint32_t tgt = tot - num;
+        int lo = x, hi = K - 1 - r;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (binom_small(K - mid, r + 1) >= tgt) lo = mid;
+            else hi = mid - 1;
         }
-        p.set(t, x);
-        ++x;
+        num -= tot - binom_small(K - lo, r + 1);
+        p.set(t, lo);
+        x = lo + 1;
     }
     return p;
 }
