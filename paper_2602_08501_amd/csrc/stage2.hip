@@ -1101,14 +1101,38 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
 {
     constexpr int N = 32 * NW;
     typedef int v4i_t __attribute__((ext_vector_type(4)));
+    // kept columns and frames are gathered in LDS and appended to the next
+    // lists with one global atomic per flush: a wave adds at most 64 of each
+    // per pass, a workgroup 256
+    constexpr int KBUF = 1024;
+    __shared__ int32_t kcol[KBUF], kfrm[KBUF];
+    __shared__ int kcnt[2];
+    __shared__ unsigned long long kbase;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per_wave = WAVE / LP;
     const int g = lane / LP, k = lane % LP, gbase = g * LP;
+    const uint64_t gmask = ((1ull << LP) - 1ull) << gbase;
     const bool merge = t + 1 < T;
     const int nfr = fl_in ? hdr[ncol(t) + 1] : hdr[0];
-    const int step = gridDim.x * (blockDim.x / WAVE) * per_wave;
-    for (int i0 = (blockIdx.x * (blockDim.x / WAVE) + wave) * per_wave; i0 < nfr; i0 += step) {
-        const int i = i0 + g;
+    const int fpb = (blockDim.x / WAVE) * per_wave;  // frames per workgroup pass
+    if (threadIdx.x == 0) kcnt[0] = kcnt[1] = 0;
+    __syncthreads();
+    auto flush = [&]() {  // every thread of the workgroup, after a barrier
+        const int nc = kcnt[0], nf = kcnt[1];
+        if (threadIdx.x == 0)
+            kbase = (nc | nf) ? atomicAdd(reinterpret_cast<unsigned long long*>(hdr + ncol(t + 1)),
+                                          ((unsigned long long)nf << 32) | (unsigned long long)nc)
+                              : 0ull;
+        __syncthreads();
+        const unsigned long long base = kbase;
+        for (int x = threadIdx.x; x < nc; x += blockDim.x) act_out[(int)(uint32_t)base + x] = kcol[x];
+        for (int x = threadIdx.x; x < nf; x += blockDim.x) fl_out[(int)(base >> 32) + x] = kfrm[x];
+        __syncthreads();
+        if (threadIdx.x == 0) kcnt[0] = kcnt[1] = 0;
+        __syncthreads();
+    };
+    for (int b0 = blockIdx.x * fpb; b0 < nfr; b0 += gridDim.x * fpb) {  // the same passes for the whole workgroup
+        const int i = b0 + wave * per_wave + g;
         const bool ok = i < nfr && k < L;
         const int s = ok ? (fl_in ? fl_in[i] : i) : 0;
         const int64_t col = (int64_t)s * L + k;
@@ -1180,36 +1204,41 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
             }
             if (out_moves) out_moves[((size_t)f * L + k) * T + t] = (int32_t)p;
         }
-        if (!merge) continue;
-        const uint64_t mvb = __ballot(moved);
-        if (mvb == 0) continue;
-        const uint64_t stb = __ballot(tg >= 0 && !moved);
-        bool stop = false;
-        int lead = -1;
-        for (int j = 0; j < L; ++j) {
-            bool eq = true;
+        if (merge) {
+            const uint64_t mvb = __ballot(moved);
+            bool keep = false;
+            if (mvb) {
+                const uint64_t stb = __ballot(tg >= 0 && !moved);
+                bool stop = false;
+                int lead = -1;
+                for (int j = 0; j < L; ++j) {
+                    bool eq = true;
 #pragma unroll
-            for (int w = 0; w < NW; ++w) eq = (__shfl(c[w], gbase + j) == c[w]) && eq;
-            if (moved && eq && j != k) {
-                if ((stb >> (gbase + j)) & 1) stop = true;
-                else if (((mvb >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
+                    for (int w = 0; w < NW; ++w) eq = (__shfl(c[w], gbase + j) == c[w]) && eq;
+                    if (moved && eq && j != k) {
+                        if ((stb >> (gbase + j)) & 1) stop = true;
+                        else if (((mvb >> (gbase + j)) & 1) && j < k && lead < 0) lead = j;
+                    }
+                }
+                keep = moved && !stop && lead < 0;
+                if (keep) tag[col] = t + 1;
+                else if (moved && !stop) tag[col] = -1 - (((t + 1) << 5) | lead);
             }
+            // into the workgroup's buffers: one LDS atomic per wave and list
+            const uint64_t kb = __ballot(keep);
+            const uint64_t fb = __ballot(k == 0 && (kb & gmask) != 0);
+            int cb = 0, fbs = 0;
+            if (lane == 0 && kb) cb = atomicAdd(&kcnt[0], __popcll(kb));
+            if (lane == 0 && fb) fbs = atomicAdd(&kcnt[1], __popcll(fb));
+            cb = __shfl(cb, 0);
+            fbs = __shfl(fbs, 0);
+            if (keep) kcol[cb + __popcll(kb & ((1ull << lane) - 1ull))] = (int32_t)col;
+            if ((fb >> lane) & 1) kfrm[fbs + __popcll(fb & ((1ull << lane) - 1ull))] = s;
         }
-        const bool keep = moved && !stop && lead < 0;
-        if (keep) tag[col] = t + 1;
-        else if (moved && !stop) tag[col] = -1 - (((t + 1) << 5) | lead);
-        // next column and frame lists: one 64-bit atomic per wave on the
-        // (frames << 32 | columns) pair of iteration t + 1
-        const uint64_t kb = __ballot(keep);
-        const uint64_t fb = __ballot(k == 0 && ((kb >> gbase) & ((1ull << LP) - 1ull)) != 0);
-        unsigned long long base = 0;
-        if (lane == 0 && kb)
-            base = atomicAdd(reinterpret_cast<unsigned long long*>(hdr + ncol(t + 1)),
-                             ((unsigned long long)__popcll(fb) << 32) | (unsigned long long)__popcll(kb));
-        base = __shfl(base, 0);
-        if (keep) act_out[(int)(uint32_t)base + __popcll(kb & ((1ull << lane) - 1ull))] = (int32_t)col;
-        if ((fb >> lane) & 1) fl_out[(int)(base >> 32) + __popcll(fb & ((1ull << lane) - 1ull))] = s;
+        __syncthreads();
+        if (merge && (kcnt[0] > KBUF - 256 || kcnt[1] > KBUF - 256)) flush();
     }
+    if (merge) flush();
 }
 
 // ---------------------------------------------------------------- select
@@ -1393,7 +1422,7 @@ void seg_prologue(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t
     hipLaunchKernelGGL(compact_kernel, dim3((unsigned)((sg.F + 255) / 256)), dim3(256), 0, s, sg.crc_ok, sg.F, w.hdr,
                        w.fid, w.slot);
     const int64_t work = sg.F * (int64_t)(L + 1) * (KP / 16);  // upper bound on the items' threads
-    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 8 * device_cus()));
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 16 * device_cus()));
     if (fl)
         hipLaunchKernelGGL(init_kernel<true>, dim3(blocks), dim3(256), 0, s, sg.llr, sg.anchors, sg.F, L, T, N, KP,
                            w.hdr, w.slot, w.fid, w.act[0], w.key64, w.metric, w.tag, w.cw, w.z, sg.out_cw, sg.out_k,
@@ -1420,7 +1449,7 @@ void launch_resolve_merge(const mpwsd_segment& sg, int L, int T, const SegWs& w,
     const int lp = lanes_per_frame(L);
     const int64_t frames_per_block = 4 * (WAVE / lp);
     const unsigned blocks = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 2 * device_cus()));
+        1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 4 * device_cus()));
     const int32_t* fl_in = t == 0 ? nullptr : w.fl[t & 1];
     int32_t* fl_out = w.fl[(t + 1) & 1];
     int32_t* act_out = w.act[(t + 1) & 1];
