@@ -184,23 +184,27 @@ int mpwsd_stage1_osd(int r, int m, int order, int L, const void* llr, int dtype,
  * picks one normal per direction space and stores each pair of translates as
  * ONE row of N/2 bits, so the search multiplies rows of length N/2 against
  * both halves of every z: half the matrix-core work of the N-long rows.
+ * Only normals below N/4 serve (the search gathers the halves without moving
+ * data between lanes); the moves of a direction space with none (e.g. 4096
+ * of the 10668 moves of RM(2, 7)) are kept apart in the layout, with their
+ * indices, and searched with plain rows into the same results.
  *
  * m: 7 or 8.  moves: HOST [P][N/8], the table given to mpwsd_decode_batch
  * (canonical order of mpwsd_build_moves).  out: HOST buffer of cap_bytes
  * bytes, or NULL for a query; it receives a self-contained byte layout that
- * the caller copies verbatim to the device and passes as the grouped and
- * grouped_chunks fields of a segment or server code.  *chunks and *bytes receive
- * the number of 128-row chunks and the layout's size.  Moves keep their
- * indices: the move logs and results do not change.
+ * the caller copies verbatim to the device and passes as the grouped,
+ * grouped_chunks and grouped_extras fields of a segment or server code.
+ * *chunks, *extras and *bytes receive the number of 128-row chunks, of moves
+ * kept apart and the layout's size.  Moves keep their indices: the move logs
+ * and results do not change.
  *
- * Returns MPWSD_ERR_UNSUPPORTED when some move has no such normal or no
- * translate partner in the table (e.g. radius >= 2 spheres, or RM(2, 7),
- * whose 4 moves that fill a quarter of the positions have none): use the
- * plain table then.  MPWSD_ERR_SIZE when out is too small (sizes are still
- * reported).  Host-only, thread-safe; O(P N) time.
+ * Returns MPWSD_ERR_UNSUPPORTED when a move has no translate partner in the
+ * table (e.g. radius >= 2 spheres): use the plain table then.  MPWSD_ERR_SIZE
+ * when out is too small (sizes are still reported).  Host-only, thread-safe;
+ * O(P N) time.
  */
 int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t* out, size_t cap_bytes,
-                      int64_t* chunks, size_t* bytes);
+                      int64_t* chunks, int64_t* extras, size_t* bytes);
 
 /*
  * One group of frames of one code for stage 2.
@@ -229,6 +233,8 @@ typedef struct mpwsd_segment {
                                   this same table (256-byte aligned), or NULL;
                                   used by the int8 search only */
     int64_t grouped_chunks;    /* its chunk count (0 when grouped is NULL) */
+    int64_t grouped_extras;    /* its count of moves kept apart (0 when
+                                  grouped is NULL) */
 } mpwsd_segment;
 
 /*
@@ -378,6 +384,7 @@ typedef struct mpwsd_server_code {
     const uint8_t* grouped;  /* device copy of mpwsd_group_moves' layout of the
                                 table, or NULL (as in mpwsd_segment) */
     int64_t grouped_chunks;
+    int64_t grouped_extras;
 } mpwsd_server_code;
 
 typedef struct mpwsd_result {

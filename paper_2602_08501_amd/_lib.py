@@ -25,7 +25,8 @@ class Segment(ctypes.Structure):
     """struct mpwsd_segment."""
     _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("llr", _p), ("dtype", _i),
                 ("F", _i64), ("anchors", _p), ("crc_ok", _p), ("out_cw", _p), ("out_k", _p),
-                ("out_metric", _p), ("out_moves", _p), ("grouped", _p), ("grouped_chunks", _i64)]
+                ("out_metric", _p), ("out_moves", _p), ("grouped", _p), ("grouped_chunks", _i64),
+                ("grouped_extras", _i64)]
 
 
 class VariantInfo(ctypes.Structure):
@@ -43,7 +44,8 @@ class Options(ctypes.Structure):
 class ServerCode(ctypes.Structure):
     """struct mpwsd_server_code."""
     _fields_ = [("r", _i), ("m", _i), ("moves", _p), ("P", _i64), ("L", _i), ("T", _i), ("crc_len", _i),
-                ("crc_poly", _u32), ("capacity", _i), ("grouped", _p), ("grouped_chunks", _i64)]
+                ("crc_poly", _u32), ("capacity", _i), ("grouped", _p), ("grouped_chunks", _i64),
+                ("grouped_extras", _i64)]
 
 
 class Result(ctypes.Structure):
@@ -73,7 +75,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_last_error.argtypes = []
         lib.mpwsd_build_moves.argtypes = [_i, _i, _p, _sz, _p, _p, _p]
         lib.mpwsd_build_sphere.argtypes = [_i, _i, _i, _p, _sz, _p, _p, _p]
-        lib.mpwsd_group_moves.argtypes = [_i, _p, _i64, _p, _sz, _p, _p]
+        lib.mpwsd_group_moves.argtypes = [_i, _p, _i64, _p, _sz, _p, _p, _p]
         lib.mpwsd_quantize_llr.argtypes = [_p, _i64, _f, _p, _p, _p]
         lib.mpwsd_stage1_scl.argtypes = [_i, _i, _i, _u32, _i, _p, _i, _i64, _p, _p, _p, _p]
         lib.mpwsd_stage1_osd.argtypes = [_i, _i, _i, _i, _p, _i, _i64, _p, _p, _p]
@@ -139,10 +141,11 @@ def mpwsd_build_sphere(r: int, m: int, radius: int, moves_ptr, cap_bytes: int):
 
 
 def mpwsd_group_moves(m: int, moves_ptr, P: int, out_ptr, cap_bytes: int):
-    """Returns (rc, chunks, bytes); out_ptr may be None for a query."""
-    chunks, nbytes = ctypes.c_int64(), ctypes.c_size_t()
-    rc = load().mpwsd_group_moves(m, moves_ptr, P, out_ptr, cap_bytes, ctypes.byref(chunks), ctypes.byref(nbytes))
-    return rc, chunks.value, nbytes.value
+    """Returns (rc, chunks, extras, bytes); out_ptr may be None for a query."""
+    chunks, extras, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    rc = load().mpwsd_group_moves(m, moves_ptr, P, out_ptr, cap_bytes, ctypes.byref(chunks), ctypes.byref(extras),
+                                  ctypes.byref(nbytes))
+    return rc, chunks.value, extras.value, nbytes.value
 
 
 def mpwsd_quantize_llr(y_ptr, n: int, scale: float, q_ptr, bad_ptr, stream: int) -> int:

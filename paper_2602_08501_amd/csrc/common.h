@@ -35,10 +35,10 @@ int device_cu_count();
 // (count read on the device): per column the minimum (S << 32 | p) is folded
 // into keys[column] with atomicMin.  zneg holds -z per column, padded to
 // max(N, 64) bytes.  grouped (device, or NULL) is the paired-half layout of
-// the same table with grouped_chunks chunks.  variant / blocks_per_cu as in
-// mpwsd_options.
+// the same table with grouped_chunks chunks and grouped_extras moves kept
+// apart.  variant / blocks_per_cu as in mpwsd_options.
 void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const uint8_t* grouped,
-                      int64_t grouped_chunks, const int32_t* act, const int32_t* count, long long* keys, int variant,
-                      int blocks_per_cu, hipStream_t s);
+                      int64_t grouped_chunks, int64_t grouped_extras, const int32_t* act, const int32_t* count,
+                      long long* keys, int variant, int blocks_per_cu, hipStream_t s);
 
 }  // namespace mpwsd

@@ -3,8 +3,7 @@
 //
 // Every move is classified by its direction space D (the span of x ^ x0 over
 // its support, x0 its smallest point; for a flat a + V of EG(m, 2), D = V).
-// A normal u can carry the move iff u is orthogonal to D and its low part
-// u mod N/4 is nonzero.  All moves with the same D go to the same normal u;
+// A normal u can carry the move iff u is orthogonal to D and 0 < u < N/4.  All moves with the same D go to the same normal u;
 // those in the half u.x = 0 become rows, and each row's partner, the move
 // translated by e_i, must be in the table too (true for the minimum-weight
 // tables: the translate of a flat is a flat with the same direction).
@@ -16,7 +15,9 @@
 // partly filled chunks, padded with all-zero rows, and a repair pass then
 // moves directions between normals to empty partly filled chunks.  Only
 // normals below N/4 are used (the same split in every lane group); they
-// cover every direction space of codimension 3 or more.
+// cover every direction space of codimension 3 or more.  The moves of a
+// direction space without one (codimension 2: e.g. 4096 of the 10668 moves
+// of RM(2, 7)) are listed apart, with their indices, for the plain search.
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -185,7 +186,7 @@ void repack(std::vector<Dir>& dirs, std::vector<Round>& rounds, int N)
 }  // namespace
 
 extern "C" int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t* out, size_t cap_bytes,
-                                 int64_t* chunks_out, size_t* bytes_out)
+                                 int64_t* chunks_out, int64_t* extras_out, size_t* bytes_out)
 {
     using namespace mpwsd;
     clear_error();
@@ -205,7 +206,12 @@ extern "C" int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t
     std::iota(order.begin(), order.end(), int64_t(0));
     std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
 
+    // only normals inside the lane groups (u < N/4): every lane group splits
+    // alike, and fewer normals fill their chunks better; they exist for every
+    // direction space of codimension 3 or more.  The moves of a direction
+    // space without one are kept apart (searched with plain rows).
     std::vector<Dir> dirs;
+    std::vector<int64_t> extra;
     for (int64_t s = 0; s < P;) {
         int64_t e = s;
         while (e < P && key[order[e]] == key[order[s]]) ++e;
@@ -213,8 +219,7 @@ extern "C" int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t
         d.begin = s;
         d.end = e;
         const uint64_t k = key[order[s]];
-        for (uint32_t u = 1; u < (uint32_t)N; ++u) {
-            if (!(u & (uint32_t)(LB - 1))) continue;
+        for (uint32_t u = 1; u < (uint32_t)LB; ++u) {
             bool ok = true;
             for (int j = 0; j < 8 && ok; ++j) ok = !par(u & (uint32_t)((k >> (8 * j)) & 0xFFu));
             if (ok) {
@@ -222,27 +227,19 @@ extern "C" int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t
                 ++d.ncand;
             }
         }
-        if (d.ncand == 0)
-            return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_group_moves: move %lld lies in no half of a lane-local cut",
-                        (long long)order[s]);
-        if ((e - s) % 2)
-            return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_group_moves: move %lld has no translate partner",
-                        (long long)order[s]);
-        d.rows = (e - s) / 2;
-        dirs.push_back(d);
+        if (d.ncand == 0) {
+            for (int64_t a = s; a < e; ++a) extra.push_back(order[a]);
+        } else {
+            if ((e - s) % 2)
+                return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_group_moves: move %lld has no translate partner",
+                            (long long)order[s]);
+            d.rows = (e - s) / 2;
+            dirs.push_back(d);
+        }
         s = e;
     }
-    // only normals inside the lane groups (u < N/4): every lane group splits
-    // alike, and fewer normals fill their chunks better; they exist for every
-    // direction space of codimension 3 or more
-    for (Dir& d : dirs) {
-        d.ncand = 0;
-        for (uint32_t u = (uint32_t)LB; u < (uint32_t)N; ++u) d.cand[u >> 6] &= ~(1ull << (u & 63));
-        for (int w = 0; w < 4; ++w) d.ncand += __builtin_popcountll(d.cand[w]);
-        if (d.ncand == 0)
-            return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_group_moves: move %lld lies in no half of a lane-local cut",
-                        (long long)order[d.begin]);
-    }
+    std::sort(extra.begin(), extra.end());
+    const int64_t E = (int64_t)extra.size();
     auto cand = [](const Dir& d, uint32_t u) { return (d.cand[u >> 6] >> (u & 63)) & 1ull; };
 
     // greedy choice of normals: rounds of (normal, directions)
@@ -334,16 +331,21 @@ extern "C" int mpwsd_group_moves(int m, const uint8_t* moves, int64_t P, uint8_t
         chunks += ((int64_t)rrows[ri].size() + kGroupRows - 1) / kGroupRows;
     }
 
-    const GroupLayout g = group_layout(m, chunks);
+    const GroupLayout g = group_layout(m, chunks, E);
     if (chunks_out) *chunks_out = chunks;
+    if (extras_out) *extras_out = E;
     if (bytes_out) *bytes_out = g.bytes;
     if (!out) return MPWSD_OK;
     if (cap_bytes < g.bytes)
         return fail(MPWSD_ERR_SIZE, "mpwsd_group_moves: needs %zu bytes, got %zu", g.bytes, cap_bytes);
 
     std::memset(out, 0, g.bytes);
-    GroupHeader h{kGroupMagic, kGroupVersion, m, N, P, chunks, KW, 0};
+    GroupHeader h{kGroupMagic, kGroupVersion, m, N, P, chunks, KW, 0, E};
     std::memcpy(out, &h, sizeof h);
+    for (int64_t x = 0; x < E; ++x) {
+        std::memcpy(out + g.xrows_off + (size_t)x * NB, moves + (size_t)extra[x] * NB, (size_t)NB);
+        ((int32_t*)(out + g.xcanon_off))[x] = (int32_t)extra[x];
+    }
     int32_t* uo = (int32_t*)(out + g.u_off);
     uint8_t* ro = out + g.rows_off;
     int32_t* co = (int32_t*)(out + g.canon_off);

@@ -19,7 +19,7 @@
 // par is the parity of the set bits.
 //
 // Blob (host or device bytes, 256-byte aligned sections):
-//     [0, 256)        header: magic, version, m, N, P, chunks, KW = N/2
+//     [0, 256)        header: magic, version, m, N, P, chunks, KW = N/2, extras
 //     u[chunks]       int32 normal of each chunk of 128 rows
 //     rows            [chunks][128][KW] int8, ready for the matrix cores:
 //                     -128 where the row's move has position k, else 0;
@@ -33,6 +33,11 @@
 //     sel             [N/4][SELW] int32, per normal u: v_perm_b32 selectors
 //                     that gather the halves from a lane group's N/4 bytes of
 //                     z and scatter them back (see below)
+//     xrows           [extras][N/8] the moves whose direction space has no
+//                     normal below N/4 (4096 of the 10668 moves of RM(2,7)),
+//                     bit-packed as in the plain table, ascending index; the
+//                     search scores them with the plain N-long rows
+//     xcanon          [extras] int32 their indices in the original table
 // Within a chunk the rows are sorted by canonical index, for both halves.
 // Normals are below N/4 (u_hi = 0), so every lane group splits alike.
 //
@@ -52,34 +57,38 @@
 namespace mpwsd {
 
 constexpr uint32_t kGroupMagic = 0x4757504Du;  // "MPWG"
-constexpr int kGroupVersion = 3;
+constexpr int kGroupVersion = 4;
 constexpr int kGroupRows = 128;                // rows per chunk
 
 struct GroupLayout {
     int N, KW, SELW;
-    int64_t chunks;
-    size_t u_off, rows_off, canon_off, sel_off, bytes;
+    int64_t chunks, extras;
+    size_t u_off, rows_off, canon_off, sel_off, xrows_off, xcanon_off, bytes;
 };
 
 inline size_t group_align(size_t x) { return (x + 255) & ~size_t(255); }
 
-inline GroupLayout group_layout(int m, int64_t chunks)
+inline GroupLayout group_layout(int m, int64_t chunks, int64_t extras)
 {
     GroupLayout g{};
     g.N = 1 << m;
     g.KW = g.N / 2;
     g.chunks = chunks;
+    g.extras = extras;
     g.u_off = 256;
     g.rows_off = g.u_off + group_align(sizeof(int32_t) * (size_t)chunks);
     g.canon_off = g.rows_off + (size_t)chunks * kGroupRows * (size_t)g.KW;
     g.SELW = g.N / 4;  // 1 + 2 (N/32) + N/16 = N/8 + 1 entries, padded
     g.sel_off = g.canon_off + (size_t)chunks * 2 * kGroupRows * sizeof(int32_t);
-    g.bytes = g.sel_off + group_align((size_t)(g.N / 4) * g.SELW * sizeof(int32_t));
+    g.xrows_off = g.sel_off + group_align((size_t)(g.N / 4) * g.SELW * sizeof(int32_t));
+    g.xcanon_off = g.xrows_off + group_align((size_t)extras * (size_t)(g.N / 8));
+    g.bytes = g.xcanon_off + group_align((size_t)extras * sizeof(int32_t));
     return g;
 }
 
-// Upper bound on the chunks of a table of P moves: P/2 rows, one partly
-// filled chunk per normal at most.
+// Bounds on the chunks of a table of P moves, `extras` of them kept apart:
+// (P - extras)/2 rows, one partly filled chunk per normal at most.
+inline int64_t group_min_chunks(int64_t P, int64_t extras) { return ((P - extras) / 2 + kGroupRows - 1) / kGroupRows; }
 inline int64_t group_max_chunks(int m, int64_t P) { return (P / 2 + kGroupRows - 1) / kGroupRows + (1 << m); }
 
 // segment swizzle of row r (see the layout above)
@@ -90,6 +99,7 @@ struct GroupHeader {
     int32_t version, m, N;
     int64_t P, chunks;
     int32_t KW, reserved;
+    int64_t extras;
 };
 
 }  // namespace mpwsd

@@ -339,7 +339,11 @@ int check_codes(const mpwsd_server_code* codes, int ncodes)
         if (!c.moves) return fail(MPWSD_ERR_ARG, "server code %d: moves is NULL", i);
         if (c.grouped) {
             if (c.m < 7) return fail(MPWSD_ERR_ARG, "server code %d: a paired-half table needs m = 7 or 8", i);
-            if (c.grouped_chunks < (c.P / 2 + 127) / 128 || c.grouped_chunks > mpwsd::group_max_chunks(c.m, c.P))
+            if (c.grouped_extras < 0 || c.grouped_extras > c.P)
+                return fail(MPWSD_ERR_ARG, "server code %d: grouped_extras %lld out of range", i,
+                            (long long)c.grouped_extras);
+            if (c.grouped_chunks < mpwsd::group_min_chunks(c.P, c.grouped_extras) ||
+                c.grouped_chunks > mpwsd::group_max_chunks(c.m, c.P))
                 return fail(MPWSD_ERR_ARG, "server code %d: grouped_chunks %lld does not fit P = %lld", i,
                             (long long)c.grouped_chunks, (long long)c.P);
             if ((reinterpret_cast<uintptr_t>(c.grouped) & 255u) != 0)
@@ -426,6 +430,7 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
         }
         // one stage-2 iteration over every active path of this code
         mpwsd::launch_search_i8(c.N, c.at<int8_t>(c.lay.zneg), c.c.moves, c.c.P, c.c.grouped, c.c.grouped_chunks,
+                                c.c.grouped_extras,
                                 act[c.cur], hdr + list_words(c.cur), c.at<long long>(c.lay.key), -1, 0, st);
         const int frames_per_block = 4 * (64 / L);
         hipLaunchKernelGGL(srv_resolve_kernel,

@@ -296,11 +296,14 @@ __device__ inline void unpack32(uint32_t x, uint32_t (&o)[8])
 // wave keeps its columns' -z fragments in VGPRs, the workgroup stages the
 // chunks through LDS, and each column's lexicographic (S, p) minimum over the
 // range is folded into keys[column] with one atomicMin.
+// pmap (or NULL): the index in the original table of row p of `moves`
+// (ascending in p), rows at or past P map to pmap_pad.
 template <int N, int NC, int NWAVES>
 __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_t* __restrict__ z,
                                            const uint8_t* __restrict__ moves, int64_t P,
                                            const int32_t* __restrict__ act, int n, long long* __restrict__ keys,
-                                           int tile, int c0, int c1)
+                                           int tile, int c0, int c1, const int32_t* __restrict__ pmap,
+                                           int64_t pmap_pad)
 {
     constexpr int KP = N < 64 ? 64 : N;         // K padded to the MFMA depth
     constexpr int RS = KP + 16;                 // LDS row stride: conflict-free 16-byte reads
@@ -424,7 +427,9 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
     // lanes li, li+16, li+32, li+48 hold the same column
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        long long v = ((long long)(run[c] >> 7) << 32) | (long long)(uint32_t)((runk[c] << 7) | (run[c] & 127));
+        int64_t p = (int64_t)((runk[c] << 7) | (run[c] & 127));
+        if (pmap) p = p < P ? (int64_t)pmap[p] : pmap_pad;
+        long long v = ((long long)(run[c] >> 7) << 32) | (long long)(uint32_t)p;
         long long o = __shfl_xor(v, 16);
         v = o < v ? o : v;
         o = __shfl_xor(v, 32);
@@ -444,18 +449,22 @@ __device__ __forceinline__ void sweep_tile(int8_t* __restrict__ lds, const int8_
 // (chunk, half); across chunks and halves, equal minima are settled by the
 // canonical indices themselves.
 struct PwTable {
-    const int32_t* u;      // [chunks]
-    const uint8_t* rows;   // [chunks][128][N/2]
-    const int32_t* canon;  // [chunks][2][128]
-    const int32_t* sel;    // [N/4][N/4] byte selectors per normal
+    const int32_t* u;       // [chunks]
+    const uint8_t* rows;    // [chunks][128][N/2]
+    const int32_t* canon;   // [chunks][2][128]
+    const int32_t* sel;     // [N/4][N/4] byte selectors per normal
     int chunks;
+    const uint8_t* xrows;   // [extras][N/8] moves kept apart (plain rows)
+    const int32_t* xcanon;  // [extras] their indices in the original table
+    int extras;
 };
 
-PwTable pw_table(const uint8_t* grouped, int m, int64_t chunks)
+PwTable pw_table(const uint8_t* grouped, int m, int64_t chunks, int64_t extras)
 {
-    const mpwsd::GroupLayout g = mpwsd::group_layout(m, chunks);
+    const mpwsd::GroupLayout g = mpwsd::group_layout(m, chunks, extras);
     return PwTable{(const int32_t*)(grouped + g.u_off), grouped + g.rows_off, (const int32_t*)(grouped + g.canon_off),
-                   (const int32_t*)(grouped + g.sel_off), (int)chunks};
+                   (const int32_t*)(grouped + g.sel_off), (int)chunks, grouped + g.xrows_off,
+                   (const int32_t*)(grouped + g.xcanon_off), (int)extras};
 }
 
 template <int WDW, int S>
@@ -795,7 +804,8 @@ __global__ __launch_bounds__(NWAVES * WAVE, (pw_waves_per_simd<N, NC, BPC>())) v
 template <int N, int NC, int NWAVES, int BPC>
 __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
     const int8_t* __restrict__ z, const uint8_t* __restrict__ moves, int64_t P,
-    const int32_t* __restrict__ act, const int32_t* __restrict__ count, long long* __restrict__ keys)
+    const int32_t* __restrict__ act, const int32_t* __restrict__ count, long long* __restrict__ keys,
+    const int32_t* __restrict__ pmap, int64_t pmap_pad)
 {
     constexpr int KP = N < 64 ? 64 : N;
     constexpr int CT = NWAVES * 16 * NC;
@@ -812,7 +822,7 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
         const int c0 = (int)(u0 % C);
         const int c1 = (int)std::min<int64_t>(C, c0 + (u1 - u0));
         u0 += c1 - c0;
-        sweep_tile<N, NC, NWAVES>(lds, z, moves, P, act, n, keys, tile, c0, c1);
+        sweep_tile<N, NC, NWAVES>(lds, z, moves, P, act, n, keys, tile, c0, c1, pmap, pmap_pad);
     }
 }
 
@@ -829,6 +839,8 @@ struct SegSearch {
     int N;
     int grouped;  // 1: pw holds the paired-half table (N = 128 or 256)
     PwTable pw;
+    const int32_t* pmap;  // plain rows only: indices of the rows, or NULL
+    int64_t pmap_pad;
 };
 constexpr int kMaxSeg = 4;
 struct MultiSearch {
@@ -878,12 +890,13 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
             continue;
         }
         switch (sg.N) {
-        case 32: sweep_tile<32, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
-        case 64: sweep_tile<64, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
-        case 128: sweep_tile<128, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1); break;
+        case 32: sweep_tile<32, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1, sg.pmap, sg.pmap_pad); break;
+        case 64: sweep_tile<64, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1, sg.pmap, sg.pmap_pad); break;
+        case 128: sweep_tile<128, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1, sg.pmap, sg.pmap_pad); break;
         default:
             if constexpr (KPMAX >= 256)
-                sweep_tile<256, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1);
+                sweep_tile<256, NC, NWAVES>(lds, sg.z, sg.moves, sg.P, sg.act, nn[si], sg.keys, tile, c0, c1,
+                                            sg.pmap, sg.pmap_pad);
             break;
         }
     }
@@ -1323,11 +1336,12 @@ int default_variant(int N) { return N >= 256 ? 1 : 0; }
 
 template <int N, int V>
 void launch_search_i8_v(const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
-                        const int32_t* count, long long* keys, hipStream_t s, int grid)
+                        const int32_t* count, long long* keys, hipStream_t s, int grid, const int32_t* pmap,
+                        int64_t pmap_pad)
 {
     constexpr Variant v = kVariants[V];
     hipLaunchKernelGGL((search_i8_kernel<N, v.nc, v.nw, v.bpc>), dim3(grid), dim3(v.nw * WAVE), 0, s, zneg, moves, P,
-                       act, count, keys);
+                       act, count, keys, pmap, pmap_pad);
 }
 
 // paired-half search: column blocks per wave capped at 4 for N = 256 (VGPRs)
@@ -1356,14 +1370,15 @@ void launch_search_pw_n(const int8_t* zneg, const PwTable& g, const int32_t* act
 
 template <int N>
 void launch_search_i8_n(const int8_t* zneg, const uint8_t* moves, int64_t P, const int32_t* act,
-                        const int32_t* count, long long* keys, hipStream_t s, int variant, int grid)
+                        const int32_t* count, long long* keys, hipStream_t s, int variant, int grid,
+                        const int32_t* pmap = nullptr, int64_t pmap_pad = 0)
 {
     switch (variant) {
-    case 0: launch_search_i8_v<N, 0>(zneg, moves, P, act, count, keys, s, grid); break;
-    case 1: launch_search_i8_v<N, 1>(zneg, moves, P, act, count, keys, s, grid); break;
-    case 2: launch_search_i8_v<N, 2>(zneg, moves, P, act, count, keys, s, grid); break;
-    case 3: launch_search_i8_v<N, 3>(zneg, moves, P, act, count, keys, s, grid); break;
-    default: launch_search_i8_v<N, 4>(zneg, moves, P, act, count, keys, s, grid); break;
+    case 0: launch_search_i8_v<N, 0>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    case 1: launch_search_i8_v<N, 1>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    case 2: launch_search_i8_v<N, 2>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    case 3: launch_search_i8_v<N, 3>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    default: launch_search_i8_v<N, 4>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
     }
 }
 
@@ -1377,6 +1392,22 @@ void launch_search_f32(const SegWs& w, const mpwsd_segment& sg, int t, hipStream
     case 7: hipLaunchKernelGGL(search_f32_kernel<128>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
     default: hipLaunchKernelGGL(search_f32_kernel<256>, dim3(grid), dim3(WAVE), 0, s, z, sg.moves, sg.P, w.act[t & 1], w.hdr, t, keys); break;
     }
+}
+
+// The moves a paired-half layout keeps apart: plain rows, searched into the
+// same keys with their original indices (ties meet the paired-half results in
+// the same atomicMin).
+void launch_extras(int N, const int8_t* zneg, const PwTable& g, int64_t P, const int32_t* act, const int32_t* count,
+                   long long* keys, int variant, int blocks_per_cu, hipStream_t s)
+{
+    if (g.extras <= 0) return;
+    const int var = variant >= 0 ? variant : default_variant(N);
+    const int pfit = (160 * 1024) / (2 * RC * (kpad(N) + 16));
+    const int grid = device_cus() * (blocks_per_cu > 0 ? std::min(blocks_per_cu, pfit) : std::min(kVariants[var].bpc, pfit));
+    if (N == 128)
+        launch_search_i8_n<128>(zneg, g.xrows, g.extras, act, count, keys, s, var, grid, g.xcanon, P);
+    else
+        launch_search_i8_n<256>(zneg, g.xrows, g.extras, act, count, keys, s, var, grid, g.xcanon, P);
 }
 
 template <int KPMAX, int V>
@@ -1513,8 +1544,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
             launch_search_f32(w, sg, t, s, device_cus() * 4);
         else
             mpwsd::launch_search_i8(N, (const int8_t*)w.z, sg.moves, sg.P, sg.grouped, sg.grouped_chunks,
-                                    w.act[t & 1], w.hdr + ncol(t), (long long*)w.key64, variant[t], blocks_per_cu[t],
-                                    s);
+                                    sg.grouped_extras, w.act[t & 1], w.hdr + ncol(t), (long long*)w.key64, variant[t],
+                                    blocks_per_cu[t], s);
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         seg_resolve(sg, L, T, w, t, merge, s);
     }
@@ -1529,10 +1560,13 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
               const int* variant, const int* blocks_per_cu, bool merge, hipStream_t s)
 {
     MultiSearch base{};
+    int owner[kMaxSeg];       // segment of each entry of the launch
+    std::vector<int> apart;   // segments whose extra moves get launches of their own
     int maxN = 0;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
         seg_prologue(segs[i], L, T, w[i], stats, base.nseg == 0, s);
+        owner[base.nseg] = i;
         SegSearch& g = base.s[base.nseg++];
         g.z = (const int8_t*)w[i].z;
         g.moves = segs[i].moves;
@@ -1540,19 +1574,44 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         g.keys = (long long*)w[i].key64;
         g.N = 1 << segs[i].m;
         g.grouped = segs[i].grouped && (g.N == 128 || g.N == 256);
-        if (g.grouped) g.pw = pw_table(segs[i].grouped, segs[i].m, segs[i].grouped_chunks);
+        g.pmap = nullptr;
+        g.pmap_pad = 0;
+        if (g.grouped)
+            g.pw = pw_table(segs[i].grouped, segs[i].m, segs[i].grouped_chunks, segs[i].grouped_extras);
         maxN = std::max(maxN, g.N);
+    }
+    // extra moves of paired-half segments: entries of the same launch while
+    // they fit, else a launch of their own
+    for (int e = 0, ne = base.nseg; e < ne; ++e) {
+        const SegSearch& g = base.s[e];
+        if (!g.grouped || g.pw.extras <= 0) continue;
+        if (base.nseg == kMaxSeg) {
+            apart.push_back(owner[e]);
+            continue;
+        }
+        owner[base.nseg] = owner[e];
+        SegSearch& x = base.s[base.nseg++];
+        x = g;
+        x.grouped = 0;
+        x.moves = g.pw.xrows;
+        x.P = g.pw.extras;
+        x.pmap = g.pw.xcanon;
+        x.pmap_pad = g.P;
     }
     for (int t = 0; t < T; ++t) {
         MultiSearch ms = base;
-        for (int i = 0, j = 0; i < nseg; ++i) {
-            if (segs[i].F == 0) continue;
-            ms.s[j].act = w[i].act[t & 1];
-            ms.s[j].count = w[i].hdr + ncol(t);
-            ++j;
+        for (int e = 0; e < ms.nseg; ++e) {
+            ms.s[e].act = w[owner[e]].act[t & 1];
+            ms.s[e].count = w[owner[e]].hdr + ncol(t);
         }
         if (ev) (void)hipEventRecord(ev[2 * t], s);
         if (ms.nseg > 0) launch_search_multi(ms, maxN, variant[t], blocks_per_cu[t], s);
+        for (int i : apart) {
+            const int N = 1 << segs[i].m;
+            launch_extras(N, (const int8_t*)w[i].z,
+                          pw_table(segs[i].grouped, segs[i].m, segs[i].grouped_chunks, segs[i].grouped_extras),
+                          segs[i].P, w[i].act[t & 1], w[i].hdr + ncol(t), (long long*)w[i].key64, -1, 0, s);
+        }
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
         for (int i = 0; i < nseg; ++i)
             if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, merge, s);
@@ -1589,7 +1648,11 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
         if (s.grouped) {
             if (s.m < 7)
                 return fail(MPWSD_ERR_ARG, "segment %d: a paired-half table needs m = 7 or 8", i);
-            if (s.grouped_chunks < (s.P / 2 + 127) / 128 || s.grouped_chunks > mpwsd::group_max_chunks(s.m, s.P))
+            if (s.grouped_extras < 0 || s.grouped_extras > s.P)
+                return fail(MPWSD_ERR_ARG, "segment %d: grouped_extras %lld out of range", i,
+                            (long long)s.grouped_extras);
+            if (s.grouped_chunks < mpwsd::group_min_chunks(s.P, s.grouped_extras) ||
+                s.grouped_chunks > mpwsd::group_max_chunks(s.m, s.P))
                 return fail(MPWSD_ERR_ARG, "segment %d: grouped_chunks %lld does not fit P = %lld", i,
                             (long long)s.grouped_chunks, (long long)s.P);
             if ((reinterpret_cast<uintptr_t>(s.grouped) & 255u) != 0)
@@ -1605,8 +1668,8 @@ namespace mpwsd {
 int device_cu_count() { return device_cus(); }
 
 void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P, const uint8_t* grouped,
-                      int64_t grouped_chunks, const int32_t* act, const int32_t* count, long long* keys, int variant,
-                      int blocks_per_cu, hipStream_t s)
+                      int64_t grouped_chunks, int64_t grouped_extras, const int32_t* act, const int32_t* count,
+                      long long* keys, int variant, int blocks_per_cu, hipStream_t s)
 {
     const int cus = device_cus();
     const bool pw = grouped && (N == 128 || N == 256);
@@ -1617,11 +1680,14 @@ void launch_search_i8(int N, const int8_t* zneg, const uint8_t* moves, int64_t P
     const int lds_fit = (160 * 1024) / lds_ws;
     const int grid = cus * (blocks_per_cu > 0 ? blocks_per_cu : std::min(kVariants[var].bpc, lds_fit));
     if (pw) {
-        const PwTable g = pw_table(grouped, N == 128 ? 7 : 8, grouped_chunks);
-        if (N == 128)
-            launch_search_pw_n<128>(zneg, g, act, count, keys, s, var, grid);
-        else
-            launch_search_pw_n<256>(zneg, g, act, count, keys, s, var, grid);
+        const PwTable g = pw_table(grouped, N == 128 ? 7 : 8, grouped_chunks, grouped_extras);
+        if (g.chunks > 0) {
+            if (N == 128)
+                launch_search_pw_n<128>(zneg, g, act, count, keys, s, var, grid);
+            else
+                launch_search_pw_n<256>(zneg, g, act, count, keys, s, var, grid);
+        }
+        launch_extras(N, zneg, g, P, act, count, keys, variant, blocks_per_cu, s);
         return;
     }
     switch (N) {

@@ -34,27 +34,31 @@ def _stream(stream):
 
 
 def group_moves_host(m: int, moves: np.ndarray):
-    """Paired-half layout of a move table (mpwsd_group_moves), as (bytes, chunks),
-    or None when the table does not group (then the plain table is searched)."""
+    """Paired-half layout of a move table (mpwsd_group_moves), as (bytes, chunks,
+    extras), or None when the table does not group (then the plain table is
+    searched)."""
     P = moves.shape[0]
     if m not in (7, 8):
         return None
-    rc, chunks, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, P, None, 0)
+    rc, chunks, extras, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, P, None, 0)
     if rc == _lib.MPWSD_ERR_UNSUPPORTED:
         return None
     check(rc)
     buf = np.zeros(nbytes, np.uint8)
-    rc, chunks, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, P, buf.ctypes.data, buf.nbytes)
+    rc, chunks, extras, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, P, buf.ctypes.data, buf.nbytes)
     check(rc)
-    return buf, chunks
+    return buf, chunks, extras
 
 
 class Code:
-    """Device-resident move table of RM(r, m): the sphere S_radius(0), and,
-    where it exists, its paired-half layout for the int8 search
-    (grouped=False keeps the plain table only)."""
+    """Device-resident move table of RM(r, m): the sphere S_radius(0), and its
+    paired-half layout for the int8 search.  grouped="auto" takes the layout
+    only when it keeps no move apart (RM(3,7), RM(3,8)): where moves are kept
+    apart (RM(2,7)) the layout's normals carry about one chunk each and the
+    plain table is faster; True takes any layout that exists; False keeps the
+    plain table only."""
 
-    def __init__(self, r: int, m: int, device="cuda:0", radius: int = 1, grouped: bool = True):
+    def __init__(self, r: int, m: int, device="cuda:0", radius: int = 1, grouped="auto"):
         self.r, self.m, self.N, self.radius = r, m, 1 << m, radius
         host = build_moves_host(r, m, radius)
         self.P = host.shape[0]
@@ -63,10 +67,12 @@ class Code:
         self.w = float(wts.mean())  # mean move weight (2^(m-r) for radius 1)
         self.moves = torch.from_numpy(host).to(device)
         self.K = sum(math.comb(m, d) for d in range(r + 1))
-        self.grouped, self.grouped_chunks = None, 0
+        self.grouped, self.grouped_chunks, self.grouped_extras = None, 0, 0
         g = group_moves_host(m, host) if grouped else None
+        if g is not None and grouped == "auto" and g[2] > 0:
+            g = None
         if g is not None:
-            buf, self.grouped_chunks = g
+            buf, self.grouped_chunks, self.grouped_extras = g
             self._grouped_store = torch.empty(buf.nbytes + 256, dtype=torch.uint8, device=device)
             off = (-self._grouped_store.data_ptr()) % 256
             self.grouped = self._grouped_store[off:off + buf.nbytes]
@@ -169,7 +175,8 @@ class Stage2:
             segs.append(Segment(code.r, code.m, code.moves.data_ptr(), code.P, _ptr(llr), self.dt, F,
                                 _ptr(anc), _ptr(ok), _ptr(o["cw"]) if o else None,
                                 _ptr(o["k"]) if o else None, _ptr(o["metric"]) if o else None,
-                                _ptr(o.get("moves")) if o else None, code.grouped_ptr(), code.grouped_chunks))
+                                _ptr(o.get("moves")) if o else None, code.grouped_ptr(), code.grouped_chunks,
+                                code.grouped_extras))
         return segs
 
     def run(self, llrs, anchors, crc_oks, stream=None, events=None, variant=-1, blocks_per_cu=0,

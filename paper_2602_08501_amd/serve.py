@@ -34,7 +34,8 @@ class Server:
         arr = (ServerCode * len(codes))()
         for i, (c, sp) in enumerate(zip(codes, specs)):
             arr[i] = ServerCode(c.r, c.m, c.moves.data_ptr(), c.P, sp["L"], sp["T"], sp.get("crc_len", 6),
-                                sp.get("crc_poly", synth.CRC6_POLY), sp["capacity"], c.grouped_ptr(), c.grouped_chunks)
+                                sp.get("crc_poly", synth.CRC6_POLY), sp["capacity"], c.grouped_ptr(), c.grouped_chunks,
+                                c.grouped_extras)
         self._arr = arr
         need = _lib.load().mpwsd_server_arena_bytes(arr, len(codes))
         if need == 0:

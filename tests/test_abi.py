@@ -109,6 +109,11 @@ def test_decode_batch_validates_before_enqueue():
         ([_seg(grouped=0x100000, grouped_chunks=368)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(grouped=0x100000, grouped_chunks=370 + 128 + 1)], 8, 8, _lib.MPWSD_ERR_ARG),
         ([_seg(grouped=0x100080, grouped_chunks=373)], 8, 8, _lib.MPWSD_ERR_ARG),
+        # moves kept apart: a count in [0, P], and the chunks must hold the rest
+        ([_seg(grouped=0x100000, grouped_chunks=373, grouped_extras=-1)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(grouped=0x100000, grouped_chunks=373, grouped_extras=94489)], 8, 8, _lib.MPWSD_ERR_ARG),
+        ([_seg(r=2, m=7, P=10668, grouped=0x100000, grouped_chunks=25, grouped_extras=4096)], 8, 8,
+         _lib.MPWSD_ERR_ARG),
     ]
     for segs, L, T, code in cases:
         if segs[-1].llr and segs[-1].moves % 4 == 0:  # size query ignores pointers
@@ -118,6 +123,8 @@ def test_decode_batch_validates_before_enqueue():
     for P in (2604, 2604 + 291648, 2604 + 291648 + 888832):
         assert _lib.mpwsd_workspace_bytes([_seg(r=2, m=6, P=P)], 8, 8) > 0, _lib.last_error()
     assert _lib.mpwsd_workspace_bytes([_seg(grouped=0x100000, grouped_chunks=373)], 8, 8) == ok
+    assert _lib.mpwsd_workspace_bytes([_seg(r=2, m=7, P=10668, grouped=0x100000, grouped_chunks=26,
+                                            grouped_extras=4096)], 8, 8) > 0, _lib.last_error()
     # workspace too small / missing / misaligned
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10000, ok - 1, None, None) == _lib.MPWSD_ERR_SIZE
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, None, ok, None, None) == _lib.MPWSD_ERR_SIZE

@@ -1,4 +1,5 @@
-"""The paired-half int8 search (tables of mpwsd_group_moves) on the device.
+"""The paired-half int8 search (tables of mpwsd_group_moves) on the device,
+with the moves it keeps apart searched with plain rows (RM(2,7)).
 
 Bit-exact against the oracle on inputs built to make many moves tie at the
 minimum (small integer LLRs), so that the smallest-index rule is exercised
@@ -52,7 +53,7 @@ def decode(cd, q, anchors, L, T, variant=-1, bpc=0):
     return {k: v.cpu().numpy() for k, v in o.items()}, st.stats.cpu().numpy()
 
 
-@pytest.mark.parametrize("r,m,F,L,T", [(3, 7, 48, 4, 4), (3, 8, 6, 4, 3)])
+@pytest.mark.parametrize("r,m,F,L,T", [(3, 7, 48, 4, 4), (3, 8, 6, 4, 3), (2, 7, 64, 4, 4)])
 def test_ties_follow_smallest_index(r, m, F, L, T):
     say("case: grouped ties", r, m, F, L, T)
     cd = code(r, m, True)
@@ -71,8 +72,8 @@ def test_ties_follow_smallest_index(r, m, F, L, T):
         assert np.array_equal(np.unpackbits(out["cw"][f], bitorder="little"), paths[kb]), f
 
 
-@pytest.mark.parametrize("wl,L,T,F", [(synth.RM37, 8, 8, 3000), (synth.RM38, 16, 4, 400)],
-                         ids=["rm37", "rm38"])
+@pytest.mark.parametrize("wl,L,T,F", [(synth.RM37, 8, 8, 3000), (synth.RM38, 16, 4, 400), (synth.RM27, 8, 8, 3000)],
+                         ids=["rm37", "rm38", "rm27"])
 def test_grouped_equals_plain_every_variant(wl, L, T, F):
     say("case: grouped vs plain", wl.r, wl.m, F)
     rng = np.random.default_rng(wl.m)
@@ -94,3 +95,42 @@ def test_grouped_equals_plain_every_variant(wl, L, T, F):
             for key in ref:
                 assert np.array_equal(got[key], ref[key]), (variant, bpc, key)
             assert np.array_equal(st, st_ref), (variant, bpc)
+
+
+def _noisy_case(rng, r, m, F, L):
+    c = random_codewords(rng, r, m, F)
+    n = 1 << m
+    y = (1 - 2.0 * c) + rng.standard_normal((F, n)) * 0.9
+    q = np.clip(np.rint(y * 10), -127, 127).astype(np.int8)
+    anchors = np.repeat(c[:, None, :], L, 1) ^ (rng.random((F, L, n)) < 0.04).astype(np.uint8)
+    return q, anchors
+
+
+def _decode_segments(codes, cases, L, T):
+    st = D.Stage2([(cd, q.shape[0]) for cd, (q, _) in zip(codes, cases)], L, T, "i8", DEV)
+    llrs = [torch.from_numpy(q).to(DEV) for q, _ in cases]
+    ancs = [torch.from_numpy(np.packbits(a, axis=-1, bitorder="little")).to(DEV) for _, a in cases]
+    outs = st.run(llrs, ancs, [None] * len(cases))
+    torch.cuda.synchronize()
+    return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs], st.stats.cpu().numpy()
+
+
+@pytest.mark.parametrize("mix", [[(2, 7), (3, 7), (2, 6)], [(2, 7), (3, 7), (2, 6), (2, 7)]],
+                         ids=["extras_in_the_launch", "extras_launched_apart"])
+def test_moves_kept_apart_in_a_mixed_launch(mix):
+    """RM(2,7) with its layout (4096 moves kept apart) beside other codes in
+    one search launch per iteration: the kept-apart moves are entries of the
+    same launch while there is room (at most 4), else launches of their own;
+    every output equals the plain tables'."""
+    say("case: kept-apart moves in a mixed launch", mix)
+    rng = np.random.default_rng(90 + len(mix))
+    L, T = 8, 6
+    cases = [_noisy_case(rng, r, m, 700, L) for r, m in mix]
+    ref, st_ref = _decode_segments([code(r, m, False) for r, m in mix], cases, L, T)
+    grouped = [code(r, m, True) for r, m in mix]
+    assert grouped[0].grouped is not None and grouped[0].grouped_extras == 4096
+    got, st = _decode_segments(grouped, cases, L, T)
+    for i in range(len(mix)):
+        for key in ref[i]:
+            assert np.array_equal(got[i][key], ref[i][key]), (mix[i], key)
+    assert np.array_equal(st, st_ref)

@@ -1,8 +1,10 @@
 """The paired-half move layout (mpwsd_group_moves) against the oracle's move
 table: every row, read back through the documented position order, must be
 exactly the oracle's move for its recorded index on half 0 and that move's
-translate by e_i on half 1; every move appears once; rows are in canonical
-order within each chunk for both halves.  Host-only (no GPU)."""
+translate by e_i on half 1; the moves kept apart are exactly those whose
+direction space has no normal below N/4, stored as the oracle's rows; every
+move appears once; rows are in canonical order within each chunk for both
+halves.  Host-only (no GPU)."""
 import ctypes
 
 import numpy as np
@@ -15,13 +17,18 @@ ROWS = 128
 
 
 def _group(m, moves):
-    rc, chunks, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, moves.shape[0], None, 0)
+    rc, chunks, extras, nbytes = _lib.mpwsd_group_moves(m, moves.ctypes.data, moves.shape[0], None, 0)
     if rc != 0:
-        return rc, None, chunks
+        return rc, None, chunks, extras
     buf = np.zeros(nbytes, np.uint8)
-    rc, chunks2, nbytes2 = _lib.mpwsd_group_moves(m, moves.ctypes.data, moves.shape[0], buf.ctypes.data, buf.nbytes)
-    assert rc == 0 and (chunks2, nbytes2) == (chunks, nbytes)
-    return rc, buf, chunks
+    rc, chunks2, extras2, nbytes2 = _lib.mpwsd_group_moves(m, moves.ctypes.data, moves.shape[0], buf.ctypes.data,
+                                                           buf.nbytes)
+    assert rc == 0 and (chunks2, extras2, nbytes2) == (chunks, extras, nbytes)
+    return rc, buf, chunks, extras
+
+
+def _al(x):
+    return (x + 255) // 256 * 256
 
 
 def _ins(e, i, v):
@@ -52,13 +59,13 @@ def _check(r, m):
     supp, _ = oracle.moves(r, m)
     table = oracle.pack_supports(m, supp)
     P = table.shape[0]
-    rc, buf, chunks = _group(m, table)
+    rc, buf, chunks, E = _group(m, table)
     assert rc == 0, _lib.last_error()
-    hdr = np.frombuffer(buf[:40].tobytes(), dtype=np.dtype([("magic", "<u4"), ("version", "<i4"), ("m", "<i4"),
+    hdr = np.frombuffer(buf[:48].tobytes(), dtype=np.dtype([("magic", "<u4"), ("version", "<i4"), ("m", "<i4"),
                                                              ("N", "<i4"), ("P", "<i8"), ("chunks", "<i8"),
-                                                             ("KW", "<i4"), ("res", "<i4")]))[0]
-    assert hdr["magic"] == 0x4757504D and hdr["version"] == 3 and hdr["m"] == m and hdr["N"] == N
-    assert hdr["P"] == P and hdr["chunks"] == chunks and hdr["KW"] == N // 2
+                                                             ("KW", "<i4"), ("res", "<i4"), ("extras", "<i8")]))[0]
+    assert hdr["magic"] == 0x4757504D and hdr["version"] == 4 and hdr["m"] == m and hdr["N"] == N
+    assert hdr["P"] == P and hdr["chunks"] == chunks and hdr["KW"] == N // 2 and hdr["extras"] == E
     KW = N // 2
     u_off = 256
     rows_off = u_off + ((4 * chunks + 255) // 256) * 256
@@ -75,14 +82,30 @@ def _check(r, m):
     sel_off = canon_off + chunks * 2 * ROWS * 4
     canon = np.frombuffer(buf[canon_off:sel_off].tobytes(), np.int32).reshape(chunks, 2, ROWS)
     LB = N // 4
-    assert buf.nbytes == sel_off + ((LB * LB * 4 + 255) // 256) * 256
+    xrows_off = sel_off + _al(LB * LB * 4)
+    xcanon_off = xrows_off + _al(E * N // 8)
+    assert buf.nbytes == xcanon_off + _al(E * 4)
     seltab = np.frombuffer(buf[sel_off:sel_off + LB * LB * 4].tobytes(), np.uint32).reshape(LB, LB)
+    xrows = buf[xrows_off:xrows_off + E * N // 8].reshape(E, N // 8)
+    xcanon = np.frombuffer(buf[xcanon_off:xcanon_off + 4 * E].tobytes(), np.int32)
+    # the moves kept apart: the oracle's rows, ascending index, and exactly the
+    # moves for which no normal 0 < u < N/4 keeps u.x constant on the support
+    assert np.array_equal(xrows, table[xcanon]) and (np.diff(xcanon) > 0).all()
+    dense_all = np.unpackbits(table, axis=-1, bitorder="little").astype(bool)
+    xs = np.arange(N)
+    us = list(range(1, LB))
+    par = np.array([[_parity(un & x) for x in xs] for un in us], bool)   # [u][x]
+    kept = set(xcanon.tolist())
+    for p in range(P):
+        sup = dense_all[p]
+        has_normal = bool((par[:, sup].all(1) | (~par[:, sup]).all(1)).any())
+        assert has_normal == (p not in kept), p
     assert ((u > 0) & (u < LB)).all()   # normals inside the lane groups
     real = canon[:, 0, :] < P
     assert np.array_equal(real, canon[:, 1, :] < P)
     assert (canon[:, 0, :][~real] == P).all() and (canon[:, 1, :][~real] == P).all() and not bits[~real].any()
-    # every move exactly once, over both halves
-    seen = np.sort(np.concatenate([canon[:, 0, :][real], canon[:, 1, :][real]]))
+    # every move exactly once, over both halves and the moves kept apart
+    seen = np.sort(np.concatenate([canon[:, 0, :][real], canon[:, 1, :][real], xcanon]))
     assert np.array_equal(seen, np.arange(P))
     # canonical order inside each chunk, both halves
     assert (real[:, :-1] >= real[:, 1:]).all()  # padding rows at the end of a chunk
@@ -131,7 +154,7 @@ def _check(r, m):
             for d in (lo, lo + (1 << S)):
                 back[d] = _perm(halves[1][k], halves[0][k], int(seltab[un, 1 + 2 * W + d]))
         assert back == zd, un
-    return chunks, P
+    return chunks, P, E
 
 
 def _perm(a, b, s):
@@ -146,32 +169,37 @@ def _perm(a, b, s):
 
 
 def test_rm37_layout():
-    chunks, P = _check(3, 7)
-    assert chunks * ROWS <= 1.02 * P / 2      # at most 2% padding
+    chunks, P, E = _check(3, 7)
+    assert E == 0 and chunks * ROWS <= 1.02 * P / 2      # at most 2% padding
+
+
+def test_rm27_layout_keeps_codimension_2_apart():
+    chunks, P, E = _check(2, 7)
+    assert P == 10668 and E == 4096 and chunks * ROWS <= 1.25 * (P - E) / 2
+
+
+def test_rm17_layout():
+    chunks, P, E = _check(1, 7)
+    assert 0 < E < P
 
 
 @pytest.mark.slow
 def test_rm38_layout():
-    chunks, P = _check(3, 8)
-    assert chunks * ROWS <= 1.02 * P / 2
+    chunks, P, E = _check(3, 8)
+    assert E == 0 and chunks * ROWS <= 1.02 * P / 2
 
 
 def test_tables_without_layout_and_errors():
-    for r, m in [(2, 7), (1, 7)]:  # moves filling a lane group, or the quarters, have no cut
-        supp, _ = oracle.moves(r, m)
-        t = oracle.pack_supports(m, supp)
-        rc, *_ = _lib.mpwsd_group_moves(m, t.ctypes.data, t.shape[0], None, 0)
-        assert rc == _lib.MPWSD_ERR_UNSUPPORTED and "cut" in _lib.last_error()
     supp, _ = oracle.moves(2, 6)
     t = oracle.pack_supports(6, supp)
     assert _lib.mpwsd_group_moves(6, t.ctypes.data, t.shape[0], None, 0)[0] == _lib.MPWSD_ERR_UNSUPPORTED
     supp, _ = oracle.moves(3, 7)
     t = oracle.pack_supports(7, supp)
-    rc, chunks, nbytes = _lib.mpwsd_group_moves(7, t.ctypes.data, t.shape[0], None, 0)
-    assert rc == 0 and nbytes > 0
+    rc, chunks, extras, nbytes = _lib.mpwsd_group_moves(7, t.ctypes.data, t.shape[0], None, 0)
+    assert rc == 0 and nbytes > 0 and extras == 0
     small = np.zeros(nbytes - 1, np.uint8)
-    rc, c2, n2 = _lib.mpwsd_group_moves(7, t.ctypes.data, t.shape[0], small.ctypes.data, small.nbytes)
-    assert rc == _lib.MPWSD_ERR_SIZE and (c2, n2) == (chunks, nbytes)
+    rc, c2, e2, n2 = _lib.mpwsd_group_moves(7, t.ctypes.data, t.shape[0], small.ctypes.data, small.nbytes)
+    assert rc == _lib.MPWSD_ERR_SIZE and (c2, e2, n2) == (chunks, extras, nbytes)
     # a table whose moves lack their translates
     rc, *_ = _lib.mpwsd_group_moves(7, t.ctypes.data, 1000, None, 0)
     assert rc == _lib.MPWSD_ERR_UNSUPPORTED
