@@ -186,9 +186,14 @@ def test_server_argument_errors():
     good = ServerCode(3, 7, 0x1000, 94488, 8, 8, 6, 0x43, 64)
     arr = (ServerCode * 1)(good)
     assert lib.mpwsd_server_arena_bytes(arr, 1) > 0
+    kept = (ServerCode * 1)(ServerCode(2, 7, 0x1000, 10668, 8, 8, 6, 0x43, 64, 0x100000, 26, 4096))
+    assert lib.mpwsd_server_arena_bytes(kept, 1) > 0, _lib.last_error()
     for bad in (ServerCode(3, 7, 0x1000, 8128, 8, 8, 6, 0x43, 64), ServerCode(3, 9, 0x1000, 94488, 8, 8, 6, 0x43, 64),
                 ServerCode(3, 7, 0x1000, 94488, 6, 8, 6, 0x43, 64), ServerCode(3, 7, 0x1000, 94488, 8, 8, 6, 0x43, 0),
-                ServerCode(3, 7, None, 94488, 8, 8, 6, 0x43, 64)):
+                ServerCode(3, 7, None, 94488, 8, 8, 6, 0x43, 64),
+                # paired-half layout: kept-apart count out of range, chunks too few for the rest
+                ServerCode(3, 7, 0x1000, 94488, 8, 8, 6, 0x43, 64, 0x100000, 373, -1),
+                ServerCode(2, 7, 0x1000, 10668, 8, 8, 6, 0x43, 64, 0x100000, 25, 4096)):
         a = (ServerCode * 1)(bad)
         assert lib.mpwsd_server_arena_bytes(a, 1) == 0
         h = ctypes.c_void_p()
