@@ -101,9 +101,36 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
         const uint8_t* a = anc + ((size_t)i * L + k) * NB;
         const int8_t* qi = q + (size_t)i * N;
         const int slot = live ? newslot[i] : 0;
+        // the paths of the other new frames become active columns: centre
+        // bits, -z and the metric, 16 positions (one 16-byte piece) at a time
+        const bool join = live && !decided;
+        const int col = slot * L + k;
         int m = 0;
-        if (live && (!decided || k == 0))
-            for (int j = 0; j < N; ++j) m += ((a[j >> 3] >> (j & 7)) & 1) ? qi[j] : 0;
+        if (live && (!decided || k == 0)) {
+            typedef int v4i_t __attribute__((ext_vector_type(4)));
+            for (int j0 = 0; j0 < KP; j0 += 16) {
+                const bool inpos = j0 < N;
+                const uint32_t bits = inpos ? *(const uint16_t*)(a + j0 / 8) : 0u;
+                const v4i_t qv = inpos ? *(const v4i_t*)(qi + j0) : v4i_t{0, 0, 0, 0};
+                v4i_t zv;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    uint32_t wz = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int v = (int8_t)((uint32_t)qv[d] >> (8 * b));
+                        const int bit = (bits >> (4 * d + b)) & 1;
+                        m += bit ? v : 0;
+                        wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
+                    }
+                    zv[d] = (int)wz;
+                }
+                if (join) {
+                    *(v4i_t*)(zneg + (size_t)col * KP + j0) = zv;
+                    if (inpos) *(uint16_t*)(cw + (size_t)col * NB + j0 / 8) = (uint16_t)bits;
+                }
+            }
+        }
         // a decided frame emits its result record
         const bool emit = decided && k == 0;
         const int rpos = wave_append(emit, &hdr[H_CCOUNT]);
@@ -115,17 +142,7 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
             r.metric = m;
             for (int b = 0; b < 32; ++b) r.cw[b] = b < NB ? a[b] : 0;
         }
-        // the paths of the other new frames become active columns
-        const bool join = live && !decided;
-        const int col = slot * L + k;
         if (join) {
-            for (int b = 0; b < NB; ++b) cw[(size_t)col * NB + b] = a[b];
-            int8_t* z = zneg + (size_t)col * KP;
-            for (int j = 0; j < KP; ++j) {
-                const int bit = j < N ? (a[j >> 3] >> (j & 7)) & 1 : 0;
-                const int v = j < N ? qi[j] : 0;
-                z[j] = (int8_t)(bit ? v : -v);  // -z
-            }
             metric[col] = m;
             citer[col] = 0;
             key[col] = LLONG_MAX;
