@@ -66,20 +66,28 @@ __global__ void srv_prep_kernel(int32_t* hdr, int nxt)
     }
 }
 
+__device__ inline uint32_t srv_quantize1(float v, float s, int32_t* __restrict__ hdr)
+{
+    if (!isfinite(v)) {
+        atomicAdd(&hdr[H_ERR], 1);
+        return 0u;
+    }
+    float t = rintf(__fmul_rn(v, s));
+    t = fminf(fmaxf(t, -127.0f), 127.0f);
+    return (uint32_t)(uint8_t)(int8_t)t;
+}
+
+// four values per thread (N is a multiple of 4, so a quadruple lies in one
+// frame and shares its scale); staging buffers are 256-byte aligned
 __global__ void srv_quantize_kernel(const float* __restrict__ y, const float* __restrict__ scale, int n, int N,
                                     int8_t* __restrict__ q, int32_t* __restrict__ hdr)
 {
-    const int64_t total = (int64_t)n * N;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-        const float v = y[i];
-        if (!isfinite(v)) {
-            q[i] = 0;
-            atomicAdd(&hdr[H_ERR], 1);
-            continue;
-        }
-        float t = rintf(__fmul_rn(v, scale[i / N]));
-        t = fminf(fmaxf(t, -127.0f), 127.0f);
-        q[i] = (int8_t)t;
+    const int64_t total4 = (int64_t)n * N / 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total4; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 v = reinterpret_cast<const float4*>(y)[i];
+        const float s = scale[(4 * i) / N];
+        reinterpret_cast<uint32_t*>(q)[i] = srv_quantize1(v.x, s, hdr) | (srv_quantize1(v.y, s, hdr) << 8) |
+                                            (srv_quantize1(v.z, s, hdr) << 16) | (srv_quantize1(v.w, s, hdr) << 24);
     }
 }
 
@@ -430,7 +438,7 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
             (void)hipMemcpyAsync(c.at<float>(c.lay.sst), p.scale, sizeof(float) * n_new, hipMemcpyHostToDevice, st);
             (void)hipMemcpyAsync(c.at<int32_t>(c.lay.newslot), p.slot, sizeof(int32_t) * n_new, hipMemcpyHostToDevice,
                                  st);
-            const int64_t tot = (int64_t)n_new * c.N;
+            const int64_t tot = (int64_t)n_new * c.N / 4;
             hipLaunchKernelGGL(srv_quantize_kernel, dim3((unsigned)std::min<int64_t>((tot + 255) / 256, 4096)),
                                dim3(256), 0, st, c.at<float>(c.lay.yst), c.at<float>(c.lay.sst), n_new, c.N,
                                c.at<int8_t>(c.lay.qst), hdr);
