@@ -192,6 +192,7 @@ __global__ __launch_bounds__(256) void init_kernel(
     const int64_t nfail = hdr[0];
     const int64_t part1 = F * PP;
     const int64_t total = part1 + nfail * L * PP;
+    const bool log16 = (L * T) % 4 == 0 && (reinterpret_cast<uintptr_t>(out_moves) & 15u) == 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         hdr[ncol(0)] = (int32_t)(nfail * L);
         if (stats) atomicAdd(&stats[0], (int32_t)nfail);
@@ -205,14 +206,25 @@ __global__ __launch_bounds__(256) void init_kernel(
         if (g < part1) {
             // ---- frame f
             const int64_t f = g / PP;
-            if (out_moves)
-                for (int e = piece; e < L * T; e += PP) out_moves[(size_t)f * L * T + e] = -1;
+            if (out_moves) {
+                if (log16) {
+                    // 16-byte stores: a frame's pieces write consecutive quads
+                    v4i* o = (v4i*)(out_moves + (size_t)f * L * T);
+                    for (int e = piece; e < L * T / 4; e += PP) o[e] = v4i{-1, -1, -1, -1};
+                } else {
+                    for (int e = piece; e < L * T; e += PP) out_moves[(size_t)f * L * T + e] = -1;
+                }
+            }
             if (slot[f] >= 0) continue;  // failing: its columns are items of the second range
             const uint32_t bits = inpos ? *(const uint16_t*)(anchors + (size_t)f * L * NB + 2 * piece) : 0u;
             int part = 0;
             if (!FLOAT && inpos) {
-                const int8_t* q = (const int8_t*)llr + (size_t)f * N + j0;
-                for (int j = 0; j < 16; ++j) part += ((bits >> j) & 1) ? q[j] : 0;
+                const v4i qv = *(const v4i*)((const int8_t*)llr + (size_t)f * N + j0);
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        part += ((bits >> (4 * d + b)) & 1) ? (int)(int8_t)((uint32_t)qv[d] >> (8 * b)) : 0;
             }
             for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
             if (inpos) *(uint16_t*)(out_cw + (size_t)f * NB + 2 * piece) = (uint16_t)bits;
@@ -1110,7 +1122,7 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
     const uint8_t* __restrict__ moves, int KP, int64_t P, int32_t* __restrict__ hdr, int t, int T,
     unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int LP,
     int32_t* __restrict__ out_moves, int32_t* __restrict__ tag, const int32_t* __restrict__ fl_in,
-    int32_t* __restrict__ fl_out, int32_t* __restrict__ act_out)
+    int32_t* __restrict__ fl_out, int32_t* __restrict__ act_out, int fcap)
 {
     constexpr int N = 32 * NW;
     typedef int v4i_t __attribute__((ext_vector_type(4)));
@@ -1126,8 +1138,13 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
     const int g = lane / LP, k = lane % LP, gbase = g * LP;
     const uint64_t gmask = ((1ull << LP) - 1ull) << gbase;
     const bool merge = t + 1 < T;
-    const int nfr = fl_in ? hdr[ncol(t) + 1] : hdr[0];
     const int fpb = (blockDim.x / WAVE) * per_wave;  // frames per workgroup pass
+    // the first pass's list entry is read before the list length is known
+    // (the two loads are in flight together); an entry past the length is
+    // stale and unused.  fcap is the list's capacity.
+    const int i0 = blockIdx.x * fpb + wave * per_wave + g;
+    int s_first = fl_in && i0 < fcap ? fl_in[i0] : i0;
+    const int nfr = fl_in ? hdr[ncol(t) + 1] : hdr[0];
     if (threadIdx.x == 0) kcnt[0] = kcnt[1] = 0;
     __syncthreads();
     auto flush = [&]() {  // every thread of the workgroup, after a barrier
@@ -1147,7 +1164,7 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
     for (int b0 = blockIdx.x * fpb; b0 < nfr; b0 += gridDim.x * fpb) {  // the same passes for the whole workgroup
         const int i = b0 + wave * per_wave + g;
         const bool ok = i < nfr && k < L;
-        const int s = ok ? (fl_in ? fl_in[i] : i) : 0;
+        const int s = !ok ? 0 : i == i0 ? s_first : fl_in ? fl_in[i] : i;
         const int64_t col = (int64_t)s * L + k;
         // every load that does not need the key is issued at once
         int tg = -1, M = 0, f = 0;
@@ -1489,7 +1506,7 @@ void launch_resolve_merge(const mpwsd_segment& sg, int L, int T, const SegWs& w,
 #define MPWSD_RESOLVE_MERGE(NW)                                                                                    \
     hipLaunchKernelGGL((resolve_merge_kernel<FLOAT, NW>), dim3(blocks), dim3(256), 0, s, w.z, cw, w.metric,       \
                        sg.moves, KP, sg.P, w.hdr, t, T, keys, w.fid, L, lp, sg.out_moves, w.tag, fl_in, fl_out,   \
-                       act_out)
+                       act_out, (int)sg.F)
     switch (N) {
     case 32: MPWSD_RESOLVE_MERGE(1); break;
     case 64: MPWSD_RESOLVE_MERGE(2); break;
