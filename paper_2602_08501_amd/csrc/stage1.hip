@@ -71,11 +71,15 @@ __device__ inline uint32_t f_pk(uint32_t a, uint32_t b)
 {
     return pk_max_i16(pk_min_i16(a, b), pk_sub_u16(0u, pk_max_i16(a, b)));
 }
-// g on both halves: b + (1 - 2 v) a, v = bit 0 (low half) / bit 1 (high half)
-__device__ inline uint32_t g_pk(uint32_t a, uint32_t b, uint32_t bits2)
+// g on both halves: b + (1 - 2 v) a, v = bit sh of w (low half) and bit
+// sh + 1 (high half), sh even.  Each bit is sign-extended to 0 or all ones and
+// ored with 1, giving the packed factors +1 / -1 of one multiply-add.
+__device__ inline uint32_t g_pk(uint32_t a, uint32_t b, uint32_t w, int sh)
 {
-    const uint32_t m = ((bits2 & 1u) ? 0x0000FFFFu : 0u) | ((bits2 & 2u) ? 0xFFFF0000u : 0u);
-    return pk_add_u16(b, pk_sub_u16(a ^ m, m));
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_sbfe((int)w, sh, 1);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_sbfe((int)w, sh + 1, 1);
+    const uint32_t sg = (lo & 0x0000FFFFu) | (hi & 0xFFFF0000u) | 0x00010001u;
+    return as_u(as_s2(a) * as_s2(sg) + as_s2(b));
 }
 
 // Polar transform x -> x F^{(x)lev} of the n = 2^lev bits held in w[]
@@ -244,7 +248,7 @@ template <int M, int L, bool FLOAT> struct Scl {
             if (sums) {
                 uint32_t s0 = 0, s1 = 0;
                 for (int k = 0; k < n; k += 2) {
-                    const uint32_t o = use_g ? g_pk(cw[k / 2], cw[(k + n) / 2], (ps[k >> 5] >> (k & 31)) & 3u)
+                    const uint32_t o = use_g ? g_pk(cw[k / 2], cw[(k + n) / 2], ps[k >> 5], k & 31)
                                              : f_pk(cw[k / 2], cw[(k + n) / 2]);
                     s0 = pk_add_u16(s0, pk_max_i16(pk_sub_u16(0u, o), 0u));
                     s1 = pk_add_u16(s1, pk_max_i16(o, 0u));
@@ -294,8 +298,9 @@ template <int M, int L, bool FLOAT> struct Scl {
     // Values of level LEV two at a time.  USEG: g (else f); TOPG: the parent
     // is the top level in its g form (recomputed from the channel).
     template <int LEV, bool USEG, bool TOPG, int PW>
-    __device__ static uint32_t pairs(const uint32_t* pa, const uint32_t* cw, const uint32_t (&vt)[TW],
-                                     const uint32_t (&ps)[PW], uint32_t* out, bool sums, V& d0, V& d1)
+    __device__ static uint32_t pairs(const uint32_t* __restrict__ pa, const uint32_t* __restrict__ cw,
+                                     const uint32_t (&vt)[TW], const uint32_t (&ps)[PW], uint32_t* __restrict__ out,
+                                     bool sums, V& d0, V& d1)
     {
         constexpr int n = 1 << LEV;
         uint32_t s0 = 0, s1 = 0, o = 0;
@@ -332,7 +337,7 @@ template <int M, int L, bool FLOAT> struct Scl {
             a = pa[(k / 2) * WAVE];
             b = pa[((k + n) / 2) * WAVE];
         }
-        if constexpr (USEG) return g_pk(a, b, (ps[k >> 5] >> (k & 31)) & 3u);
+        if constexpr (USEG) return g_pk(a, b, ps[k >> 5], k & 31);
         else return f_pk(a, b);
     }
 
@@ -340,7 +345,7 @@ template <int M, int L, bool FLOAT> struct Scl {
     __device__ static uint32_t top_pair_t(const uint32_t* cw, int k, const uint32_t (&vt)[TW])
     {
         const uint32_t a = cw[k / 2], b = cw[(k + N / 2) / 2];
-        if constexpr (TOPG) return g_pk(a, b, (vt[k >> 5] >> (k & 31)) & 3u);
+        if constexpr (TOPG) return g_pk(a, b, vt[k >> 5], k & 31);
         else return f_pk(a, b);
     }
 
@@ -362,7 +367,7 @@ template <int M, int L, bool FLOAT> struct Scl {
     __device__ static uint32_t top_pair_v(const uint32_t* cw, int k, int i, const uint32_t (&vt)[TW])
     {
         const uint32_t a = cw[k / 2], b = cw[(k + N / 2) / 2];
-        return i < N / 2 ? f_pk(a, b) : g_pk(a, b, (vt[k >> 5] >> (k & 31)) & 3u);
+        return i < N / 2 ? f_pk(a, b) : g_pk(a, b, vt[k >> 5], k & 31);
     }
     __device__ static uint32_t top_pair(const uint32_t* cw, int k, int i, const uint32_t (&ub)[NW])
     {
