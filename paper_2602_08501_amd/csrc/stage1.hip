@@ -296,7 +296,9 @@ template <int M, int L, bool FLOAT> struct Scl {
     }
 
     // Values of level LEV two at a time.  USEG: g (else f); TOPG: the parent
-    // is the top level in its g form (recomputed from the channel).
+    // is the top level in its g form (recomputed from the channel).  The
+    // parent rows, the output rows and the channel never overlap (distinct
+    // levels), which lets the parent reads be issued ahead of the stores.
     template <int LEV, bool USEG, bool TOPG, int PW>
     __device__ static uint32_t pairs(const uint32_t* __restrict__ pa, const uint32_t* __restrict__ cw,
                                      const uint32_t (&vt)[TW], const uint32_t (&ps)[PW], uint32_t* __restrict__ out,
