@@ -215,13 +215,16 @@ typedef struct mpwsd_segment {
                                   or mpwsd_build_sphere */
     int64_t P;                 /* number of moves: the size of one of those
                                   tables for RM(r, m) (checked) */
-    const void* llr;           /* device [F][N]: int8 q or float y */
+    const void* llr;           /* device [F][N]: int8 q (16-byte aligned) or
+                                  float y (4-byte aligned) */
     int dtype;                 /* MPWSD_I8 or MPWSD_F32 */
     int64_t F;                 /* frames */
-    const uint8_t* anchors;    /* device [F][L][N/8], list of stage 1 */
+    const uint8_t* anchors;    /* device [F][L][N/8], list of stage 1
+                                  (4-byte aligned) */
     const uint8_t* crc_ok;     /* device [F]; 1 = decided by stage 1.  NULL:
                                   every frame goes to stage 2 (always-on) */
-    uint8_t* out_cw;           /* device out [F][N/8]: decision for every frame */
+    uint8_t* out_cw;           /* device out [F][N/8]: decision for every frame
+                                  (4-byte aligned) */
     int32_t* out_k;            /* device out [F]: chosen path (0 when stage 1
                                   decided); may be NULL */
     int32_t* out_metric;       /* device out [F]: metric of the decision (int8:

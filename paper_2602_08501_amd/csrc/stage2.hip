@@ -1662,6 +1662,11 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
             return fail(MPWSD_ERR_ARG, "segment %d: null pointer", i);
         if (check_ptrs && (reinterpret_cast<uintptr_t>(s.moves) & 3u) != 0)
             return fail(MPWSD_ERR_ARG, "segment %d: moves must be 4-byte aligned", i);
+        // int8 q is read 16 positions at a time, anchors and decisions two bytes at a time
+        if (check_ptrs && (reinterpret_cast<uintptr_t>(s.llr) & (s.dtype == MPWSD_I8 ? 15u : 3u)) != 0)
+            return fail(MPWSD_ERR_ARG, "segment %d: llr must be %d-byte aligned", i, s.dtype == MPWSD_I8 ? 16 : 4);
+        if (check_ptrs && ((reinterpret_cast<uintptr_t>(s.anchors) | reinterpret_cast<uintptr_t>(s.out_cw)) & 3u) != 0)
+            return fail(MPWSD_ERR_ARG, "segment %d: anchors and out_cw must be 4-byte aligned", i);
         if (s.grouped) {
             if (s.m < 7)
                 return fail(MPWSD_ERR_ARG, "segment %d: a paired-half table needs m = 7 or 8", i);

@@ -129,6 +129,14 @@ def test_decode_batch_validates_before_enqueue():
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10000, ok - 1, None, None) == _lib.MPWSD_ERR_SIZE
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, None, ok, None, None) == _lib.MPWSD_ERR_SIZE
     assert _lib.mpwsd_decode_batch([_seg()], 8, 8, 0x10010, ok, None, None) == _lib.MPWSD_ERR_ARG
+    # pointer alignment (int8 q: 16 bytes, float y: 4, anchors and decisions: 4); the size query
+    # does not look at pointers
+    for seg in (_seg(llr=0x2008), _seg(llr=0x2002, dtype=1), _seg(anchors=0x3002), _seg(out_cw=0x4002)):
+        assert _lib.mpwsd_workspace_bytes([seg], 8, 8) > 0
+        assert _lib.mpwsd_decode_batch([seg], 8, 8, 0x10000, 1 << 40, None, None) == _lib.MPWSD_ERR_ARG
+        assert "aligned" in _lib.last_error()
+    for seg in (_seg(llr=0x2010), _seg(llr=0x2004, dtype=1)):
+        assert _lib.mpwsd_workspace_bytes([seg], 8, 8) > 0
 
 
 def test_stage1_validates_before_enqueue():
