@@ -1333,8 +1333,10 @@ __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __res
                 if (v < mb) { mb = v; kb = k; }
             }
         }
-        const uint8_t* c = cw + ((size_t)s * L + kb) * NB;
-        for (int b = 0; b < NB; ++b) out_cw[(size_t)f * NB + b] = c[b];
+        // NB is a multiple of 4; both rows are 4-byte aligned
+        const uint32_t* c = reinterpret_cast<const uint32_t*>(cw + ((size_t)s * L + kb) * NB);
+        uint32_t* o = reinterpret_cast<uint32_t*>(out_cw + (size_t)f * NB);
+        for (int b = 0; b < NB / 4; ++b) o[b] = c[b];
         if (out_k) out_k[f] = kb;
         if (out_metric) out_metric[f] = mb;
     }
