@@ -1664,7 +1664,7 @@ int validate(const mpwsd_segment* segs, int nseg, int L, int T, bool check_ptrs)
             return fail(MPWSD_ERR_ARG, "segment %d: null pointer", i);
         if (check_ptrs && (reinterpret_cast<uintptr_t>(s.moves) & 3u) != 0)
             return fail(MPWSD_ERR_ARG, "segment %d: moves must be 4-byte aligned", i);
-        // int8 q is read 16 positions at a time, anchors and decisions two bytes at a time
+        // int8 q is read 16 positions at a time, anchors and decisions in 2- and 4-byte words
         if (check_ptrs && (reinterpret_cast<uintptr_t>(s.llr) & (s.dtype == MPWSD_I8 ? 15u : 3u)) != 0)
             return fail(MPWSD_ERR_ARG, "segment %d: llr must be %d-byte aligned", i, s.dtype == MPWSD_I8 ? 16 : 4);
         if (check_ptrs && ((reinterpret_cast<uintptr_t>(s.anchors) | reinterpret_cast<uintptr_t>(s.out_cw)) & 3u) != 0)
