@@ -113,6 +113,13 @@ template <int NW> __device__ inline void polar_bits(uint32_t (&w)[NW], int lev)
 struct Sched {
     uint8_t v[256];
 };
+// The CRC test as a linear map: with the register starting at 0, its final
+// value is the xor of one fixed word per set information bit.  Row b holds,
+// over the N decided bits (32 per word), the positions whose word has bit b
+// set, so register bit b is the parity of (u & row b).
+struct CrcRows {
+    uint32_t w[16][8];
+};
 constexpr int KIND_R0 = 1, KIND_REP = 2;
 
 // Value of lane `lane ^ X` (X < 32): DPP quad permutes for X = 1, 2, else a
@@ -554,7 +561,7 @@ template <int M, int L, bool FLOAT> struct Scl {
 template <int M, int L, bool FLOAT>
 __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F,
                                                    uint64_t info0, uint64_t info1, uint64_t info2, uint64_t info3,
-                                                   int crc_len, uint32_t crc_poly, Sched sched,
+                                                   int crc_len, CrcRows crc, Sched sched,
                                                    uint8_t* __restrict__ anchors, uint8_t* __restrict__ crc_ok,
                                                    int32_t* __restrict__ pm_out)
 {
@@ -671,14 +678,12 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
         if (rank == 0) {
             int ok = 0;
             if (crc_len > 0) {
-                const uint32_t top = 1u << (crc_len - 1), mask = (1u << crc_len) - 1u;
                 uint32_t reg = 0;
-                for (int j = 0; j < N; ++j) {
-                    if (((info[j >> 6] >> (j & 63)) & 1ull) == 0) continue;
-                    const uint32_t bit = (ub[j >> 5] >> (j & 31)) & 1u;
-                    const uint32_t fb = ((reg & top) ? 1u : 0u) ^ bit;
-                    reg = (reg << 1) & mask;
-                    if (fb) reg ^= crc_poly & mask;
+                for (int b = 0; b < crc_len; ++b) {
+                    uint32_t x = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) x ^= ub[w] & crc.w[b][w];
+                    reg |= (uint32_t)(__popc(x) & 1) << b;
                 }
                 ok = reg == 0;
             }
@@ -744,6 +749,28 @@ Sched make_sched(int m, const uint64_t* info)
     return sc;
 }
 
+// Rows of the CRC test (CrcRows).  The register is fed the information bits
+// in ascending position: fb = (top bit) xor bit, shift left, xor the
+// polynomial when fb is set.  A single 1 followed by t zeros leaves
+// step0^t(poly), step0 being a step with input 0; walking the information
+// positions from the last one down, t grows by one per position.
+CrcRows make_crc_rows(int m, const uint64_t* info, int crc_len, uint32_t poly)
+{
+    CrcRows cr{};
+    if (crc_len <= 0) return cr;
+    const uint32_t top = 1u << (crc_len - 1), mask = (crc_len == 32) ? ~0u : (1u << crc_len) - 1u;
+    uint32_t cur = poly & mask;
+    for (int j = (1 << m) - 1; j >= 0; --j) {
+        if (((info[j >> 6] >> (j & 63)) & 1ull) == 0) continue;
+        for (int b = 0; b < crc_len; ++b)
+            if ((cur >> b) & 1u) cr.w[b][j >> 5] |= 1u << (j & 31);
+        const bool fb = (cur & top) != 0;
+        cur = (cur << 1) & mask;
+        if (fb) cur ^= poly & mask;
+    }
+    return cr;
+}
+
 template <int M, int L, bool FL>
 void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, uint32_t poly, uint8_t* anchors,
                  uint8_t* crc_ok, int32_t* pm, hipStream_t s)
@@ -751,7 +778,8 @@ void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, 
     constexpr int64_t per = WAVE / L;
     const int64_t blocks = (F + per - 1) / per;
     hipLaunchKernelGGL((scl_kernel<M, L, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, info[0], info[1],
-                       info[2], info[3], crc_len, poly, make_sched(M, info), anchors, crc_ok, pm);
+                       info[2], info[3], crc_len, make_crc_rows(M, info, crc_len, poly), make_sched(M, info), anchors,
+                       crc_ok, pm);
 }
 
 template <int M, bool FL>

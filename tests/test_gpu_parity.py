@@ -86,8 +86,15 @@ def test_quantizer_parity_and_nonfinite():
 
 
 # ---------------------------------------------------------------- stage 1
+# the last two: a 16-bit CRC (x^16 + x^12 + x^5 + 1) and an 11-bit one (x^11 + x^10 + x^9 + x^5 + 1)
+# whose test rows span every word of the decided bits
+CRC16_RM37 = dataclasses.replace(synth.RM37, k_pay=48, crc_len=16, crc_poly=0x11021)
+CRC11_RM38 = dataclasses.replace(synth.RM38, k_pay=82, crc_len=11, crc_poly=0xE21)
+
+
 @pytest.mark.parametrize("wl,L,F", [(synth.RM26, 4, 300), (synth.RM37, 8, 256), (synth.RM27, 8, 128),
-                                    (synth.RM38, 16, 24), (synth.RM37, 1, 64), (synth.RM37, 32, 16)])
+                                    (synth.RM38, 16, 24), (synth.RM37, 1, 64), (synth.RM37, 32, 16),
+                                    (CRC16_RM37, 8, 256), (CRC11_RM38, 8, 48)])
 @pytest.mark.parametrize("dtype", ["i8", "f32"])
 def test_stage1_parity(wl, L, F, dtype):
     say("case: stage1", wl, L, F, dtype)
