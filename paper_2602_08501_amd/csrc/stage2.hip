@@ -291,6 +291,19 @@ __global__ __launch_bounds__(256) void init_kernel(
 }
 
 // ---------------------------------------------------------------- int8 search
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  The searches number their workgroups so that
+// those of one XCD take consecutive work ranges: a column tile's -z, and the
+// chunks it sweeps, are then fetched into one L2 instead of into several.
+// A bijection of [0, gridDim.x) for any grid size.
+__device__ inline int64_t xcd_block()
+{
+    constexpr int64_t X = 8;
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t per = G / X, rem = G % X, x = b % X;
+    return x * per + (x < rem ? x : rem) + b / X;
+}
+
 // Unpack 32 bits (LSB first) into 32 bytes: a set bit becomes 0x80 (-128),
 // a clear bit 0.  Each nibble, placed at bits 7..10, spreads to bit 7 of four
 // bytes with one full-rate 24-bit multiply by 1 + 2^7 + 2^14 + 2^21 (the four
@@ -801,8 +814,9 @@ __global__ __launch_bounds__(NWAVES * WAVE, (pw_waves_per_simd<N, NC, BPC>())) v
     const int tiles = (n + CT - 1) / CT;
     const int C = g.chunks;
     const int64_t U = (int64_t)tiles * C;
-    int64_t u0 = U * blockIdx.x / gridDim.x;
-    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    const int64_t wg = xcd_block();
+    int64_t u0 = U * wg / gridDim.x;
+    const int64_t u1 = U * (wg + 1) / gridDim.x;
     while (u0 < u1) {
         const int tile = (int)(u0 / C);
         const int c0 = (int)(u0 % C);
@@ -827,8 +841,9 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_kernel(
     const int tiles = (n + CT - 1) / CT;
     const int C = (int)((P + RC - 1) / RC);
     const int64_t U = (int64_t)tiles * C;
-    int64_t u0 = U * blockIdx.x / gridDim.x;
-    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    const int64_t wg = xcd_block();
+    int64_t u0 = U * wg / gridDim.x;
+    const int64_t u1 = U * (wg + 1) / gridDim.x;
     while (u0 < u1) {
         const int tile = (int)(u0 / C);
         const int c0 = (int)(u0 % C);
@@ -880,8 +895,9 @@ __global__ __launch_bounds__(NWAVES * WAVE, BPC) void search_i8_multi_kernel(Mul
         ustart[i + 1] = ustart[i] + (int64_t)tiles * cc[i];
     }
     const int64_t U = ustart[kMaxSeg];
-    int64_t u0 = U * blockIdx.x / gridDim.x;
-    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    const int64_t wg = xcd_block();
+    int64_t u0 = U * wg / gridDim.x;
+    const int64_t u1 = U * (wg + 1) / gridDim.x;
     while (u0 < u1) {
         int si = 0;
 #pragma unroll
@@ -994,8 +1010,9 @@ __global__ __launch_bounds__(WAVE) void search_f32_kernel(const float* __restric
     const int tiles = (n + CT - 1) / CT;
     const int C = (int)((P + MC - 1) / MC);
     const int64_t U = (int64_t)tiles * C;
-    int64_t u0 = U * blockIdx.x / gridDim.x;
-    const int64_t u1 = U * (blockIdx.x + 1) / gridDim.x;
+    const int64_t wg = xcd_block();
+    int64_t u0 = U * wg / gridDim.x;
+    const int64_t u1 = U * (wg + 1) / gridDim.x;
     while (u0 < u1) {
         const int tile = (int)(u0 / C);
         const int c0 = (int)(u0 % C);
