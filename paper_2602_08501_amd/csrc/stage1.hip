@@ -571,7 +571,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     using S = typename K::S;
     using Key = typename K::Key;
     constexpr int N = K::N, NW = K::NW, G = K::G;
-    __shared__ typename K::Smem sm;
+    __shared__ __attribute__((aligned(16))) typename K::Smem sm;
 
     const int lane = threadIdx.x;
     const int slot = lane % L;
@@ -580,10 +580,23 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     const bool live = frame < F;
     const uint64_t info[4] = {info0, info1, info2, info3};
 
-    // stage the channel values of the wave's frames (coalesced)
-    for (int e = lane; e < G * N; e += WAVE) {
-        const int64_t fr = (int64_t)blockIdx.x * G + e / N;
-        sm.ch[(e / N) * K::CHS + e % N] = (S)(fr < F ? A::load_ch(llr, fr * N + e % N) : (V)0);
+    // stage the channel values of the wave's frames (coalesced); int8 q four
+    // values per lane and load when it is 4-byte aligned, widened to two
+    // int16 pairs (a frame's N values never share a word with another frame)
+    if (!FLOAT && (reinterpret_cast<uintptr_t>(llr) & 3u) == 0) {
+        for (int e = 4 * lane; e < G * N; e += 4 * WAVE) {
+            const int64_t fr = (int64_t)blockIdx.x * G + e / N;
+            const uint32_t w = fr < F ? *reinterpret_cast<const uint32_t*>((const int8_t*)llr + fr * N + e % N) : 0u;
+            auto wide = [](uint32_t b) { return (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)b; };
+            uint32_t* d = reinterpret_cast<uint32_t*>(sm.ch + (e / N) * K::CHS + e % N);
+            d[0] = wide(w) | (wide(w >> 8) << 16);
+            d[1] = wide(w >> 16) | (wide(w >> 24) << 16);
+        }
+    } else {
+        for (int e = lane; e < G * N; e += WAVE) {
+            const int64_t fr = (int64_t)blockIdx.x * G + e / N;
+            sm.ch[(e / N) * K::CHS + e % N] = (S)(fr < F ? A::load_ch(llr, fr * N + e % N) : (V)0);
+        }
     }
     __syncthreads();
 

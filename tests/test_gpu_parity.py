@@ -119,6 +119,26 @@ def test_stage1_parity(wl, L, F, dtype):
         assert ok[f] == oracle.crc_ok(u[0][A], wl.crc_len, wl.crc_poly), f
 
 
+
+def test_stage1_unaligned_llr():
+    # int8 q one byte off a 4-byte boundary takes the byte-wise channel staging;
+    # the lists must be those of the aligned copy
+    say("case: stage1 unaligned q")
+    wl, L, F = synth.RM37, 8, 96
+    c, y, q = workload(wl, 5, F)
+    cd = code(wl.r, wl.m)
+    qd = torch.from_numpy(q).to(DEV)
+    buf = torch.zeros(F * wl.N + 1, dtype=torch.int8, device=DEV)
+    buf[1:].copy_(qd.reshape(-1))
+    q1 = buf[1:].view(F, wl.N)
+    assert q1.data_ptr() % 4 == 1
+    a = D.stage1(cd, L, qd, wl.crc_len, wl.crc_poly, want_pm=True)
+    b = D.stage1(cd, L, q1, wl.crc_len, wl.crc_poly, want_pm=True)
+    torch.cuda.synchronize()
+    for key in ("anchors", "crc_ok", "pm"):
+        assert torch.equal(a[key], b[key]), key
+
+
 # ---------------------------------------------------------------- stage 2 (end to end)
 E2E = [
     ("rm26_cfg", synth.RM26, 4, 4, 500),
