@@ -21,8 +21,9 @@
  * Bit vectors are one byte per bit (0/1) throughout, for readability.
  *
  * Parity status: every exported function is pinned by a CPU test against
- * closed forms, brute force, or invariants the paper states; see the test
- * files for the pin of each function.
+ * closed forms, brute force, or invariants the paper states; the binary32
+ * mode of every function that has one is pinned against a separate numpy
+ * float32 evaluation of the same definitions.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -662,14 +663,24 @@ int orc_stage2_frame(int mode, int n, int64_t P, int w, const uint16_t* supp,
 }
 
 /* ------------------------------------------------------------------------- */
-/* Alg. 1 as printed, in double precision: per iteration and active path,
- * filter the m moves with the largest correlation gain
- *     G(w) = sum_{j in supp(w)} -2 y_j x_j(c)        (Eq. (5))
- * (ties to the smaller index), then search those m by the exact squared
- * distance ||y - x(c xor w)||^2 computed from scratch, accept on strict
- * decrease, deactivate otherwise, and stop all paths early when none moved.
- * The final estimate is the path of smallest distance.  Used to check that
- * the filter does not change the result of the full-argmin form.           */
+/* The filtered form of the search (Sec. III-B, Eq. (4)-(5), and the filter
+ * size rule of Sec. IV-A), in double precision.  Every path is improved on
+ * its own, from its anchor, for at most J rounds.  In a round, with c the
+ * path's current centre:
+ *   - each move w gets its correlation gain G(w) = sum over supp(w) of
+ *     -2 y_j x_j(c) (Eq. (5));
+ *   - the mfilt moves of largest gain are kept (equal gains: smaller index
+ *     first);
+ *   - for each kept move the squared distance ||y - x(c xor w)||^2 is
+ *     evaluated directly, and the smallest one (equal distances: smaller
+ *     index) is taken;
+ *   - if it is strictly below ||y - x(c)||^2 the centre moves there and the
+ *     round logs the move; otherwise the path ends and logs -1 from here on.
+ * A stopped path would meet the same centre again, so rounds in which no
+ * path moves change nothing and need no separate stopping rule.  The
+ * estimate is the path whose final centre is closest to y, the first such
+ * path on equal distances.  This form exists to check that the filter does
+ * not change the outcome of the full-argmin form used everywhere else.   */
 typedef struct { double g; int64_t p; } gain_item;
 static int cmp_gain(const void* a, const void* b)
 {
@@ -679,58 +690,56 @@ static int cmp_gain(const void* a, const void* b)
     return x->p < y->p ? -1 : (x->p > y->p ? 1 : 0);
 }
 
+static double sq_dist(int n, const double* y, const uint8_t* c)
+{
+    double e = 0.0;
+    for (int j = 0; j < n; ++j) { double d = y[j] - (c[j] ? -1.0 : 1.0); e += d * d; }
+    return e;
+}
+
 int orc_stage2_alg1(int n, int64_t P, int w, const uint16_t* supp, const double* y,
                     int L, const uint8_t* anchors, int J, int64_t mfilt,
                     uint8_t* paths_out, int32_t* logs)
 {
-    uint8_t* act = (uint8_t*)malloc((size_t)L);
-    uint8_t* cand = (uint8_t*)malloc((size_t)n);
+    uint8_t* trial = (uint8_t*)malloc((size_t)n);
     gain_item* gi = (gain_item*)malloc(sizeof(gain_item) * (size_t)P);
+    int64_t keep = mfilt < P ? mfilt : P;
     memcpy(paths_out, anchors, (size_t)L * n);
-    for (int k = 0; k < L; ++k) act[k] = 1;
     for (int i = 0; i < L * J; ++i) logs[i] = -1;
-    for (int it = 0; it < J; ++it) {
-        int updated = 0;
-        for (int k = 0; k < L; ++k) {
-            if (!act[k]) continue;
-            uint8_t* c = paths_out + (size_t)k * n;
+    for (int k = 0; k < L; ++k) {
+        uint8_t* c = paths_out + (size_t)k * n;
+        for (int round = 0; round < J; ++round) {
             for (int64_t p = 0; p < P; ++p) {
                 double g = 0.0;
                 for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) {
                     int j = supp[p * w + i];
-                    double x = c[j] ? -1.0 : 1.0;
-                    g += -2.0 * y[j] * x;
+                    g += -2.0 * y[j] * (c[j] ? -1.0 : 1.0);
                 }
-                gi[p].g = g; gi[p].p = p;
+                gi[p].g = g;
+                gi[p].p = p;
             }
             qsort(gi, (size_t)P, sizeof(gain_item), cmp_gain);
-            int64_t mm = mfilt < P ? mfilt : P;
-            double cur = orc_metric(ORC_F64, n, y, c);
-            double bestd = 0.0; int64_t best = -1;
-            for (int64_t t = 0; t < mm; ++t) {
+            int64_t best = -1;
+            double best_d = 0.0;
+            for (int64_t t = 0; t < keep; ++t) {
                 int64_t p = gi[t].p;
-                memcpy(cand, c, (size_t)n);
-                for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) cand[supp[p * w + i]] ^= 1;
-                double d = orc_metric(ORC_F64, n, y, cand);
-                if (best < 0 || d < bestd || (d == bestd && p < best)) { best = p; bestd = d; }
+                memcpy(trial, c, (size_t)n);
+                for (int i = 0; i < w && supp[p * w + i] != ORC_SUPP_END; ++i) trial[supp[p * w + i]] ^= 1;
+                double d = sq_dist(n, y, trial);
+                if (best < 0 || d < best_d || (d == best_d && p < best)) { best = p; best_d = d; }
             }
-            if (best >= 0 && bestd < cur) {
-                for (int i = 0; i < w && supp[best * w + i] != ORC_SUPP_END; ++i) c[supp[best * w + i]] ^= 1;
-                logs[k * J + it] = (int32_t)best;
-                updated = 1;
-            } else {
-                act[k] = 0;
-            }
+            if (best < 0 || !(best_d < sq_dist(n, y, c))) break;
+            for (int i = 0; i < w && supp[best * w + i] != ORC_SUPP_END; ++i) c[supp[best * w + i]] ^= 1;
+            logs[k * J + round] = (int32_t)best;
         }
-        if (!updated) break;
     }
     int kb = 0;
-    double bd = orc_metric(ORC_F64, n, y, paths_out);
+    double bd = sq_dist(n, y, paths_out);
     for (int k = 1; k < L; ++k) {
-        double d = orc_metric(ORC_F64, n, y, paths_out + (size_t)k * n);
+        double d = sq_dist(n, y, paths_out + (size_t)k * n);
         if (d < bd) { bd = d; kb = k; }
     }
-    free(act); free(cand); free(gi);
+    free(trial); free(gi);
     return kb;
 }
 
