@@ -18,11 +18,15 @@ RM(2,7) frames at 2.5 dB without CRC, OSD(k) stage 1 with L=8 anchors, stage
 2 on every frame, T=4, 10668 moves).
 
 Prints one JSON line.  The roofline entry is for the stage-2 move-search
-kernel: dense int8 MFMA work 2 P N per searched path and iteration, over
-that kernel's launch durations measured with HIP events on the stream it
-runs on; its "executed" entry gives the MFMA work the kernel really runs,
-which for paired-half tables (RM(3,7), RM(3,8)) is about half of 2 P N.  The
-CPU baseline is the test oracle on a bounded sample of the same frames.
+kernel: the method's own work per searched path and iteration, P w adds and
+P compares (w the mean move weight), over that kernel's launch durations
+measured with HIP events on the stream it runs on, against the int8 matrix
+core peak that carries it.  Two more counts sit beside it: "executed", the
+int8 MFMA operations the kernel issues (rows of N/2 against both halves for
+the paired-half tables of RM(3,7) and RM(3,8), rows of N otherwise), and
+"dense_equivalent", 2 P N per path, the dense product W Z.  The CPU
+baseline is the test oracle on bounded samples of the same frames, on one
+core and on all the cores it may use.
 """
 from __future__ import annotations
 
@@ -52,7 +56,8 @@ def parse():
     ap.add_argument("--ebn0", type=float, default=None, help="override the workload's Eb/N0")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-frames", type=int, default=-1,
-                    help="oracle sample size in frames (0 = skip; default: the whole batch, 4096 for rm38)")
+                    help="oracle sample size in frames on all cores, one eighth of it on one core (0 = skip; "
+                         "default: up to 32768, 2048 for rm38)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a reference dispatch of "
@@ -106,7 +111,8 @@ def recorded_traffic(workload_name):
 
 def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1, osd=None):
     """The oracle on the first frames of every code's batch (the sample split
-    evenly over the codes), int8 arithmetic, whole two-stage decode."""
+    evenly over the codes), int8 arithmetic, whole two-stage decode, with
+    `threads` threads (one frame per task)."""
     import oracle
     qs, parts = [], []
     for (wl, F), y in zip(segs, ys):
@@ -132,7 +138,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus %d requested); "
-              "the decoder shards by frame with no communication, see DESIGN.md" % args.gpus,
+              "the decoder shards by frame with no communication between GPUs" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -241,17 +247,23 @@ def main():
                                   ms if nseg == 1 else None,
                                   c_init=None if osd is None else float(complexity.c_osd(c.K, osd)))
                 for c, (_, F), x in zip(codes, segs, per_seg_stats)]
-    dense_ops = sum(2.0 * c.P * c.N * cols for c, cols in zip(codes, per_seg_cols))  # per launch
     launches = np.array([[evs[k][2 * t].elapsed_time(evs[k][2 * t + 1]) for t in range(T)]
                          for k in range(args.steps)]).mean(0)
-    achieved = float(dense_ops.sum() / (launches.sum() * 1e-3) / 1e12)
+    secs = launches.sum() * 1e-3
+    # the method's work per searched path and iteration: P w adds + P compares
+    alg_per_path = [c.P * (c.w + 1.0) for c in codes]
+    alg_ops = sum(a * cols for a, cols in zip(alg_per_path, per_seg_cols))  # per launch
+    achieved = float(alg_ops.sum() / secs / 1e12)
+    dense_per_path = [2.0 * c.P * c.N for c in codes]
+    dense_ops = sum(d * cols for d, cols in zip(dense_per_path, per_seg_cols))
+    dense = float(dense_ops.sum() / secs / 1e12)
     # int8 MFMA work the kernels execute: a paired-half table runs rows of N/2
     # against both halves (chunks * 128 rows * 2 * N/2 MACs per path), the
     # plain table N-long rows padded to 128-move chunks
     exec_per_path = [(2.0 * c.grouped_chunks * 128 * 2 * (c.N // 2)) if c.grouped is not None
                      else (2.0 * -(-c.P // 128) * 128 * max(c.N, 64)) for c in codes]
     exec_ops = sum(e * cols for e, cols in zip(exec_per_path, per_seg_cols))
-    executed = float(exec_ops.sum() / (launches.sum() * 1e-3) / 1e12)
+    executed = float(exec_ops.sum() / secs / 1e12)
     fer, fer1 = [], []
     for i in range(nseg):
         cw = np.unpackbits(st.outs[i]["cw"].cpu().numpy(), axis=-1, bitorder="little")
@@ -288,11 +300,15 @@ def main():
                      "kernel": ("search_i8_multi_kernel" if nseg > 1 else
                                 "search_pw_kernel" if codes[0].grouped is not None else "search_i8_kernel"),
                      "launch_ms": launches.tolist(),
-                     "work_per_launch": "2*P*N per searched path (dense int8 MACs x2)",
+                     "searched_paths_per_launch": [int(x) for x in sum(per_seg_cols)],
+                     "work_per_launch": "P*w adds + P compares per searched path (the method's count)",
+                     "ops_per_path": alg_per_path,
                      "executed": {"achieved": executed, "frac": executed / MI355X_INT8_DENSE_TOPS,
                                   "ops_per_path": exec_per_path,
-                                  "note": "MFMA ops the kernel runs; a paired-half table needs about half "
-                                          "of 2*P*N, so achieved/peak above counts each row twice"}},
+                                  "note": "int8 MFMA ops the kernel issues (2 per MAC)"},
+                     "dense_equivalent": {"achieved": dense, "frac": dense / MI355X_INT8_DENSE_TOPS,
+                                          "ops_per_path": dense_per_path,
+                                          "note": "2*P*N per path: the dense product W Z"}},
         "complexity_ed_units": ed_units if nseg > 1 else ed_units[0],
         "wall_s": wall,
         "ms_per_step_eager": ms_eager,
@@ -301,10 +317,17 @@ def main():
                          for t, (v, b) in enumerate(zip(variant, bpc))],
     }
     if args.cpu_frames < 0:
-        args.cpu_frames = {"rm38": 4096, "rm26s2": 8192, "rm27osd": 16384}.get(args.workload, F_total)
+        args.cpu_frames = {"rm38": 2048, "rm26s2": 4096, "rm27osd": 8192}.get(args.workload, min(F_total, 32768))
     if args.cpu_frames > 0:
-        thr = args.cpu_threads or min(16, os.cpu_count() or 1)
-        res["cpu_baseline"] = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr, radius, osd)
+        # all the cores this process may use (at most 16 threads: the host CPU
+        # share of one GPU), and one core on a smaller sample
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        thr = args.cpu_threads or min(16, avail)
+        cb = cpu_baseline(segs, ys, L, T, args.cpu_frames, thr, radius, osd)
+        one = cpu_baseline(segs, ys, L, T, max(1, args.cpu_frames // 8), 1, radius, osd)
+        cb.update({"host_cpus": os.cpu_count(), "affinity_cpus": avail,
+                   "single_core": {"value": one["value"], "unit": one["unit"], "cores": 1, "sample": one["sample"]}})
+        res["cpu_baseline"] = cb
     print(json.dumps(res))
 
 

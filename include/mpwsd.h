@@ -24,10 +24,17 @@
  *     first bit = highest degree, no reflection, zero init, no final xor.
  *   - LLR inputs are either int8 q (dtype MPWSD_I8) or float y (MPWSD_F32),
  *     row-major [F][N].  A positive value favours bit 0 (x = 1 - 2c).
+ *     int8 values are read in the symmetric range [-127, 127]: every call
+ *     reads a q of -128 as -127 (mpwsd_quantize_llr never writes -128).  The
+ *     symmetric range keeps the negation z = q (1 - 2c) exact in int8 and
+ *     bounds every stage-1 value by 127 N.
  *   - Device pointers are plain device addresses (hipMalloc or a framework
  *     tensor); the caller owns every buffer.  The library allocates no device
- *     memory and keeps no mutable global state; all work is enqueued on the
- *     caller's stream and nothing synchronises it.
+ *     memory; all work is enqueued on the caller's stream and nothing
+ *     synchronises it.  Its only process-wide host state is a set of memo
+ *     tables filled once under a lock and never changed after: the weight
+ *     distribution of each code whose sphere sizes were needed, and the
+ *     compute-unit count of each device.  They affect no result.
  *   - Every call returns MPWSD_OK (0) or a negative error code; arguments are
  *     validated before anything is enqueued, and on error nothing is written.
  *     mpwsd_last_error() describes the last failure of the calling thread.
@@ -124,7 +131,8 @@ int mpwsd_quantize_llr(const float* y, int64_t n, float scale, int8_t* q,
  * in exact int32 arithmetic, float LLRs in IEEE binary32 without
  * contraction.
  *
- * llr: device [F][N], int8 (MPWSD_I8) or float (MPWSD_F32).
+ * llr: device [F][N], int8 (MPWSD_I8, read in [-127, 127]) or float
+ *      (MPWSD_F32).
  * anchors: device out [F][L][N/8]: the list in ascending (PM, slot) order,
  *          the initial list of Sec. III-B.
  * crc_ok: device out [F]: 1 iff the first list entry's information bits
@@ -160,7 +168,8 @@ int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L,
  *      sum_{c_j = 1} q_j (exact); float input ||y - x(c)||^2 in IEEE
  *      binary32, summed in ascending position order without contraction.
  *
- * llr: device [F][N], int8 (MPWSD_I8) or float (MPWSD_F32), finite.
+ * llr: device [F][N], int8 (MPWSD_I8, read in [-127, 127]) or float
+ *      (MPWSD_F32), finite.
  * anchors: device out [F][L][N/8] (bit j of a row is byte j/8, bit j%8).
  * metric: device out [F][L] int32 (float input: the binary32 bit pattern),
  *         or NULL.
@@ -214,9 +223,14 @@ typedef struct mpwsd_segment {
     const uint8_t* moves;      /* device [P][N/8], the table of mpwsd_build_moves
                                   or mpwsd_build_sphere */
     int64_t P;                 /* number of moves: the size of one of those
-                                  tables for RM(r, m) (checked) */
-    const void* llr;           /* device [F][N]: int8 q (16-byte aligned) or
-                                  float y (4-byte aligned) */
+                                  tables for RM(r, m) (checked; for a radius
+                                  >= 2 table the first check of a code walks
+                                  its 2^K codewords on the host once per
+                                  process, as mpwsd_build_sphere does, which
+                                  fills the same memo: build the table before
+                                  recording a graph) */
+    const void* llr;           /* device [F][N]: int8 q (16-byte aligned; read
+                                  in [-127, 127]) or float y (4-byte aligned) */
     int dtype;                 /* MPWSD_I8 or MPWSD_F32 */
     int64_t F;                 /* frames */
     const uint8_t* anchors;    /* device [F][L][N/8], list of stage 1

@@ -1,5 +1,5 @@
-// Device helper shared by the batch decoder and the server: applying an
-// accepted move w_p to a stage-2 column (Eq. (4): the centre moves to
+// Device helpers shared by the kernels: reading caller int8 LLRs, and (batch
+// decoder and server) applying an accepted move w_p to a stage-2 column (Eq. (4): the centre moves to
 // c xor w_p; the stored -z changes sign on supp(w_p)).
 #pragma once
 
@@ -8,6 +8,17 @@
 #include <cstdint>
 
 namespace mpwsd {
+
+// Caller int8 LLRs are read in [-127, 127]: in each byte of x a value of
+// -128 (0x80) becomes -127 (0x81), the others are unchanged.  The symmetric
+// range keeps every negation of z exact in int8.
+__device__ inline uint32_t read_q4(uint32_t x)
+{
+    const uint32_t t = x ^ 0x80808080u;                         // 0x80 bytes become 0
+    const uint32_t nz = ((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t;  // bit 7: byte of t nonzero
+    return x + ((~nz & 0x80808080u) >> 7);
+}
+__device__ inline int read_q1(int8_t v) { return v < -127 ? -127 : (int)v; }
 
 // Negate the int8 lanes of x whose bit is set in the low 4 bits of nib
 // (two's complement per byte, no carry between bytes).

@@ -29,6 +29,7 @@
 #include <climits>
 #include <cstring>
 
+#include "apply.h"
 #include "common.h"
 
 namespace {
@@ -239,8 +240,8 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
             qs[j] = v < 0.0f ? -1 : 0;  // hard decision only
             mag = __float_as_uint(fabsf(v));
         } else {
-            const int8_t v = ((const int8_t*)llr)[f * N + j];
-            qs[j] = v;
+            const int v = mpwsd::read_q1(((const int8_t*)llr)[f * N + j]);
+            qs[j] = (int8_t)v;
             mag = (uint32_t)(v < 0 ? -(int)v : (int)v);
         }
         if (FLOAT) keys[j] = ((uint64_t)(0xFFFFFFFFu - mag) << 32) | (uint32_t)j;
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
             const int e = lane * W + h;
             uint32_t key = 0xFFFFu;
             if (e < N) {
-                const int v = ((const int8_t*)llr)[f * N + e];
+                const int v = mpwsd::read_q1(((const int8_t*)llr)[f * N + e]);
                 key = ((255u - (uint32_t)(v < 0 ? -v : v)) << 8) | (uint32_t)e;
             }
             x[h] = key;

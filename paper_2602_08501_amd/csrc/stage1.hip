@@ -18,6 +18,7 @@
 #include <cstring>
 #include <type_traits>
 
+#include "apply.h"
 #include "common.h"
 
 namespace {
@@ -27,8 +28,8 @@ constexpr int WAVE = 64;
 template <bool FLOAT> struct Arith;
 template <> struct Arith<false> {
     using V = int32_t;        // LLR arithmetic
-    using S = int16_t;        // LDS storage: |l| <= 127 * 2^(m - level) <= 32512
-    __device__ static V load_ch(const void* p, int64_t i) { return (V)((const int8_t*)p)[i]; }
+    using S = int16_t;        // LDS storage: |l| <= 127 * 2^(m - level) <= 32512 (q read in [-127, 127])
+    __device__ static V load_ch(const void* p, int64_t i) { return (V)mpwsd::read_q1(((const int8_t*)p)[i]); }
     __device__ static uint32_t key_bits(V pm) { return (uint32_t)pm; }
 };
 template <> struct Arith<true> {
@@ -586,7 +587,8 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     if (!FLOAT && (reinterpret_cast<uintptr_t>(llr) & 3u) == 0) {
         for (int e = 4 * lane; e < G * N; e += 4 * WAVE) {
             const int64_t fr = (int64_t)blockIdx.x * G + e / N;
-            const uint32_t w = fr < F ? *reinterpret_cast<const uint32_t*>((const int8_t*)llr + fr * N + e % N) : 0u;
+            const uint32_t w =
+                fr < F ? mpwsd::read_q4(*reinterpret_cast<const uint32_t*>((const int8_t*)llr + fr * N + e % N)) : 0u;
             auto wide = [](uint32_t b) { return (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)b; };
             uint32_t* d = reinterpret_cast<uint32_t*>(sm.ch + (e / N) * K::CHS + e % N);
             d[0] = wide(w) | (wide(w >> 8) << 16);

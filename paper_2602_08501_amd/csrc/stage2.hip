@@ -221,10 +221,12 @@ __global__ __launch_bounds__(256) void init_kernel(
             if (!FLOAT && inpos) {
                 const v4i qv = *(const v4i*)((const int8_t*)llr + (size_t)f * N + j0);
 #pragma unroll
-                for (int d = 0; d < 4; ++d)
+                for (int d = 0; d < 4; ++d) {
+                    const uint32_t wq = mpwsd::read_q4((uint32_t)qv[d]);
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        part += ((bits >> (4 * d + b)) & 1) ? (int)(int8_t)((uint32_t)qv[d] >> (8 * b)) : 0;
+                        part += ((bits >> (4 * d + b)) & 1) ? (int)(int8_t)(wq >> (8 * b)) : 0;
+                }
             }
             for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
             if (inpos) *(uint16_t*)(out_cw + (size_t)f * NB + 2 * piece) = (uint16_t)bits;
@@ -260,7 +262,8 @@ __global__ __launch_bounds__(256) void init_kernel(
                     const v4i qv = *(const v4i*)((const int8_t*)llr + (size_t)f * N + j0);
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
-                        uint32_t wq = (uint32_t)qv[d], wz = 0;
+                        const uint32_t wq = mpwsd::read_q4((uint32_t)qv[d]);
+                        uint32_t wz = 0;
 #pragma unroll
                         for (int b = 0; b < 4; ++b) {
                             const int v = (int8_t)(wq >> (8 * b));
@@ -1283,7 +1286,13 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
             if ((fb >> lane) & 1) kfrm[fbs + __popcll(fb & ((1ull << lane) - 1ull))] = s;
         }
         __syncthreads();
-        if (merge && (kcnt[0] > KBUF - 256 || kcnt[1] > KBUF - 256)) flush();
+        // every wave reads the counts between this barrier and the next one
+        // (flush's first, or the one below), before any wave of the next pass
+        // adds to them, so all waves take the same branch
+        if (merge) {
+            if (kcnt[0] > KBUF - 256 || kcnt[1] > KBUF - 256) flush();
+            else __syncthreads();
+        }
     }
     if (merge) flush();
 }

@@ -106,9 +106,13 @@ class Graph:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if not h:
+            return
+        self.handle = None
+        try:
             _lib.mpwsd_graph_destroy(h)
-            self.handle = None
+        except (AttributeError, TypeError, OSError):
+            pass  # interpreter teardown: the module or the library is already gone
 
 
 def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: int = 0x43,

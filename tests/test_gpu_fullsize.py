@@ -1,5 +1,6 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (whole step recorded as a HIP graph, autotuned search tiles), checked
+times (whole step recorded as a HIP graph, autotuned search tiles, and for
+RM(3,7) also without move logs, as bench.py runs it), checked
 against the oracle on sampled frames (every frame is decoded independently,
 so the oracle decodes the sampled rows alone)."""
 import dataclasses
@@ -24,19 +25,25 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_pipeline(wl, F, L, T, seed):
+def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None):
+    """The step bench.py times: quantize, stage 1 and stage 2 recorded as one
+    HIP graph with autotuned per-iteration tiles (or the given ones), replayed
+    twice.  bench.py itself runs it with want_moves=False (no move logs)."""
     pay, c, y = synth.generate(wl, seed, 0, F)
     code = D.Code(wl.r, wl.m, DEV)
     y_d = torch.from_numpy(y).to(DEV)
     q = torch.empty(y.shape, dtype=torch.int8, device=DEV)
     s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=DEV),
           "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)}
-    st = D.Stage2([(code, F)], L, T, "i8", DEV)
+    st = D.Stage2([(code, F)], L, T, "i8", DEV, want_moves=want_moves)
     scale = float(wl.llr_scale)
     D.quantize(y_d, scale, out=q)
     D.stage1(code, L, q, wl.crc_len, wl.crc_poly, out=s1)
     torch.cuda.synchronize()
-    variant, bpc = autotune.tune(st, [q], [s1["anchors"]], [s1["crc_ok"]], reps=1, use_cache=False)
+    if tiles is None:
+        variant, bpc = autotune.tune(st, [q], [s1["anchors"]], [s1["crc_ok"]], reps=1, use_cache=False)
+    else:
+        variant, bpc = tiles
 
     def record(raw):
         D.quantize(y_d, scale, out=q, raw_stream=raw)
@@ -63,7 +70,8 @@ def check_sample(wl, L, T, out, rows):
     anc = np.unpackbits(out["anchors"][rows], axis=-1, bitorder="little")
     assert np.array_equal(out["crc_ok"][rows], ref["crc_ok"])
     assert np.array_equal(anc, ref["anchors"])
-    assert np.array_equal(out["moves"][rows], ref["logs"])
+    if "moves" in out:
+        assert np.array_equal(out["moves"][rows], ref["logs"])
     assert np.array_equal(cw, ref["c"])
     assert np.array_equal(out["k"][rows], ref["k"])
     assert np.array_equal(out["metric"][rows], ref["metric"].astype(np.int32))
@@ -87,6 +95,14 @@ def test_rm37_bench_size():
                                    rng.choice(np.nonzero(out["crc_ok"])[0], 64, replace=False),
                                    [0, F - 1]]))
     check_sample(wl, L, T, out, rows)
+    # exactly what bench.py times: the same graph without move logs
+    say("case: RM(3,7) 65536 frames, bench configuration (no move logs)")
+    c2, y2, out2, stats2, _ = run_pipeline(wl, F, L, T, 0, want_moves=False, tiles=tiles)
+    assert "moves" not in out2
+    for k in ("cw", "k", "metric", "crc_ok", "anchors", "q"):
+        assert np.array_equal(out2[k], out[k]), k
+    assert np.array_equal(stats2, stats)
+    check_sample(wl, L, T, out2, rows)
 
 
 def test_rm38_config_size():

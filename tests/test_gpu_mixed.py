@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import oracle
+from paper_2602_08501_amd import autotune
 from paper_2602_08501_amd import decoder as D
 from paper_2602_08501_amd import synth
 
@@ -104,3 +105,44 @@ def test_mixed_full_size_config():
         assert np.array_equal(np.unpackbits(o["cw"][rows], axis=-1, bitorder="little"), ref["c"])
         assert np.array_equal(o["moves"][rows], ref["logs"])
         assert np.array_equal(o["k"][rows], ref["k"])
+        assert np.array_equal(o["metric"][rows], ref["metric"].astype(np.int32))
+    # the configuration bench.py --workload mixed times: quantize, stage 1 and
+    # one stage-2 call over the three codes recorded as a HIP graph, autotuned
+    # per-iteration tiles, no move logs; replayed twice
+    say("case: mixed full size, bench configuration (graph, autotuned tiles, no move logs)")
+    ys = [torch.from_numpy(synth.generate(wl, 0, 0, F)[2]).to(DEV) for wl, F in zip(wls, Fs)]
+    qs = [torch.empty(y.shape, dtype=torch.int8, device=DEV) for y in ys]
+    s1s = [{"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=DEV),
+            "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)} for (wl, code, q, s1, c), F in zip(segs, Fs)]
+    st = D.Stage2([(seg[1], F) for seg, F in zip(segs, Fs)], L, T, "i8", DEV, want_moves=False)
+
+    def stage1_all(raw=None):
+        for (wl, code, q, s1, c), y, qq, ss in zip(segs, ys, qs, s1s):
+            kw = {} if raw is None else {"raw_stream": raw}
+            D.quantize(y, float(wl.llr_scale), out=qq, **kw)
+            D.stage1(code, L, qq, wl.crc_len, wl.crc_poly, out=ss, **kw)
+
+    stage1_all()
+    torch.cuda.synchronize()
+    variant, bpc = autotune.tune(st, qs, [x["anchors"] for x in s1s], [x["crc_ok"] for x in s1s], reps=1,
+                                 use_cache=False)
+    say("  tiles", variant, bpc)
+
+    def record(raw):
+        stage1_all(raw)
+        st.run(qs, [x["anchors"] for x in s1s], [x["crc_ok"] for x in s1s], variant=variant, blocks_per_cu=bpc,
+               raw_stream=raw)
+
+    g = D.Graph(record)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    assert np.array_equal(st.stats.cpu().numpy(), stats)
+    for i, ((wl, code, q, s1, c), o) in enumerate(zip(segs, outs)):
+        assert np.array_equal(qs[i].cpu().numpy(), q.cpu().numpy())
+        assert np.array_equal(s1s[i]["anchors"].cpu().numpy(), s1["anchors"].cpu().numpy())
+        b = {k: v.cpu().numpy() for k, v in st.outs[i].items()}
+        assert "moves" not in b
+        for k in ("cw", "k", "metric"):
+            assert np.array_equal(b[k], o[k]), (i, k)
+    del g
