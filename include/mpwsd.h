@@ -301,6 +301,30 @@ int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, int T,
                        hipStream_t stream);
 
 /*
+ * mpwsd_decode_batch_noalloc - mpwsd_decode_batch without a workspace
+ * argument, for callers that cannot allocate device memory (code recorded
+ * into a HIP graph, tight serving loops, hosts that forbid allocation).
+ *
+ * Same segments, L, T, stats, results and errors as mpwsd_decode_batch; the
+ * workspace is instead a fixed array of MPWSD_NOALLOC_SCRATCH_BYTES bytes
+ * inside the library, one per GPU, that each GPU holds from the library's
+ * first use on it until the process ends.  The call allocates nothing:
+ * no hipMalloc or hipFree and no allocating library routine; the first call
+ * on a device looks up that device's array address once.
+ *
+ * Limit: MPWSD_ERR_SIZE (nothing enqueued) when mpwsd_workspace_bytes of
+ * the same arguments exceeds MPWSD_NOALLOC_SCRATCH_BYTES (64 MiB: about
+ * 49000 RM(3,7) frames at L = 8, or 13000 RM(3,8) frames at L = 16).
+ * Every call on one GPU uses that GPU's single array, and nothing in it
+ * carries over between calls: calls whose work may overlap on one GPU (on
+ * different streams, or from several host threads) race and must be
+ * serialised by the caller, e.g. by issuing them on one stream.
+ */
+#define MPWSD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mpwsd_decode_batch_noalloc(const mpwsd_segment* segs, int nseg, int L, int T,
+                               int32_t* stats, hipStream_t stream);
+
+/*
  * Tuning of the stage-2 move search.  The search kernel comes in a few tile
  * shapes ("variants": column blocks of 16 per wave x waves per workgroup);
  * all give bit-identical results, only their speed differs with the code

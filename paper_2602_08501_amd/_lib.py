@@ -16,6 +16,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mpwsd.h")
 
 MPWSD_OK, MPWSD_ERR_ARG, MPWSD_ERR_SIZE, MPWSD_ERR_DEVICE, MPWSD_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 MPWSD_I8, MPWSD_F32 = 0, 1
+MPWSD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _p, _i, _i64, _u32, _f, _sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32,
                                ctypes.c_float, ctypes.c_size_t)
@@ -82,6 +83,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_workspace_bytes.argtypes = [ctypes.POINTER(Segment), _i, _i, _i]
         lib.mpwsd_workspace_bytes.restype = _sz
         lib.mpwsd_decode_batch.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p, _p]
+        lib.mpwsd_decode_batch_noalloc.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _p]
         lib.mpwsd_decode_batch_ex.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p,
                                               ctypes.POINTER(Options), _p]
         lib.mpwsd_search_variants.argtypes = [ctypes.POINTER(VariantInfo), _i]
@@ -99,7 +101,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_serve_trace.argtypes = [_p, _i64, _p, _p, _p, _p, ctypes.POINTER(_p), ctypes.POINTER(Result)]
         for name in ("mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_group_moves", "mpwsd_quantize_llr",
                      "mpwsd_stage1_scl", "mpwsd_stage1_osd", "mpwsd_decode_batch",
-                     "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
+                     "mpwsd_decode_batch_noalloc", "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
                      "mpwsd_graph_launch", "mpwsd_graph_destroy", "mpwsd_server_create", "mpwsd_server_submit",
                      "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"):
             getattr(lib, name).restype = _i
@@ -176,6 +178,10 @@ def mpwsd_decode_batch(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, s
     arr = segments_array(segs)
     return load().mpwsd_decode_batch(arr, len(segs), L, T, ws_ptr, ws_bytes, stats_ptr, stream)
 
+
+def mpwsd_decode_batch_noalloc(segs, L: int, T: int, stats_ptr, stream) -> int:
+    arr = segments_array(segs)
+    return load().mpwsd_decode_batch_noalloc(arr, len(segs), L, T, stats_ptr, stream)
 
 
 def mpwsd_decode_batch_ex(segs, L: int, T: int, ws_ptr, ws_bytes: int, stats_ptr, variant=-1,

@@ -32,7 +32,6 @@
 #include <climits>
 #include <cstring>
 #include <mutex>
-#include <vector>
 
 #include "apply.h"
 #include "common.h"
@@ -101,11 +100,15 @@ SegWs carve(const mpwsd_segment& sg, int L, int T, uint8_t* base)
 int device_cus()
 {
     static std::mutex mu;
-    static std::vector<int> cache;
+    static int cache[64];
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev < 0 || dev >= 64) {
+        int cus = 0;
+        return hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0
+                   ? cus : 256;
+    }
     std::lock_guard<std::mutex> g(mu);
-    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
     if (!cache[dev]) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
@@ -1606,7 +1609,8 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
 {
     MultiSearch base{};
     int owner[kMaxSeg];       // segment of each entry of the launch
-    std::vector<int> apart;   // segments whose extra moves get launches of their own
+    int apart[kMaxSeg];       // segments whose extra moves get launches of their own
+    int napart = 0;
     int maxN = 0;
     for (int i = 0; i < nseg; ++i) {
         if (segs[i].F == 0) continue;
@@ -1631,7 +1635,7 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         const SegSearch& g = base.s[e];
         if (!g.grouped || g.pw.extras <= 0) continue;
         if (base.nseg == kMaxSeg) {
-            apart.push_back(owner[e]);
+            apart[napart++] = owner[e];
             continue;
         }
         owner[base.nseg] = owner[e];
@@ -1651,7 +1655,8 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
         }
         if (ev) (void)hipEventRecord(ev[2 * t], s);
         if (ms.nseg > 0) launch_search_multi(ms, maxN, variant[t], blocks_per_cu[t], s);
-        for (int i : apart) {
+        for (int a = 0; a < napart; ++a) {
+            const int i = apart[a];
             const int N = 1 << segs[i].m;
             launch_extras(N, (const int8_t*)w[i].z,
                           pw_table(segs[i].grouped, segs[i].m, segs[i].grouped_chunks, segs[i].grouped_extras),
@@ -1764,9 +1769,11 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
 {
     int rc = validate(segs, nseg, L, T, true);
     if (rc != MPWSD_OK) return rc;
-    // search tiles of every iteration
-    std::vector<int> variant(T, opt ? opt->search_variant : -1), bpc(T, opt ? opt->blocks_per_cu : 0);
+    // search tiles of every iteration (T <= 64)
+    int variant[64], bpc[64];
     for (int t = 0; t < T; ++t) {
+        variant[t] = opt ? opt->search_variant : -1;
+        bpc[t] = opt ? opt->blocks_per_cu : 0;
         if (opt && opt->iter_variant) variant[t] = opt->iter_variant[t];
         if (opt && opt->iter_blocks_per_cu) bpc[t] = opt->iter_blocks_per_cu[t];
         if (variant[t] < -1 || variant[t] >= kNumVariants)
@@ -1789,19 +1796,22 @@ int decode(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t w
     for (int i = 0; i < nseg; ++i) any = any || segs[i].F > 0;
     if (stats && !any) hipLaunchKernelGGL(stats_zero_kernel, dim3(1), dim3(128), 0, stream, stats, 2 + T);
     uint8_t* base = (uint8_t*)ws;
-    std::vector<SegWs> w(nseg);
-    for (int i = 0; i < nseg; ++i) {
-        w[i] = carve(segs[i], L, T, base);
-        base += w[i].bytes;
+    if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8) {
+        SegWs w[kMaxSeg];
+        for (int i = 0; i < nseg; ++i) {
+            w[i] = carve(segs[i], L, T, base);
+            base += w[i].bytes;
+        }
+        return run_multi(segs, nseg, L, T, w, stats, (opt && opt->events) ? opt->events : nullptr, variant, bpc,
+                         merge, stream);
     }
-    if (nseg > 1 && nseg <= kMaxSeg && segs[0].dtype == MPWSD_I8)
-        return run_multi(segs, nseg, L, T, w.data(), stats, (opt && opt->events) ? opt->events : nullptr,
-                         variant.data(), bpc.data(), merge, stream);
     bool first = true;
     for (int i = 0; i < nseg; ++i) {
+        const SegWs w = carve(segs[i], L, T, base);
+        base += w.bytes;
         if (segs[i].F == 0) continue;
         hipEvent_t* ev = (opt && opt->events) ? opt->events + (size_t)2 * T * i : nullptr;
-        rc = run_segment(segs[i], L, T, w[i], stats, first, ev, variant.data(), bpc.data(), merge, stream);
+        rc = run_segment(segs[i], L, T, w, stats, first, ev, variant, bpc, merge, stream);
         first = false;
         if (rc != MPWSD_OK) return rc;
     }
@@ -1814,6 +1824,63 @@ extern "C" int mpwsd_decode_batch(const mpwsd_segment* segs, int nseg, int L, in
 {
     mpwsd::clear_error();
     return decode(segs, nseg, L, T, ws, ws_bytes, stats, nullptr, stream);
+}
+
+// ---------------------------------------------------------------- no-alloc form
+// The workspace of mpwsd_decode_batch_noalloc: a fixed device array of the
+// library, one copy per GPU, held until the process ends.  Host code never
+// passes its name to a kernel or a copy: the name is a host-side stand-in,
+// and the device address of each GPU's copy is looked up once per device.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static_assert(kNoallocScratchBytes == MPWSD_NOALLOC_SCRATCH_BYTES, "scratch size as declared in mpwsd.h");
+static __device__ __align__(256) uint8_t scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the
+// first call on each device), or nullptr with the error recorded.
+void* scratch_ptr()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch_noalloc: no current device (or device id >= %d)",
+                    kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            mpwsd::fail(MPWSD_ERR_DEVICE, "mpwsd_decode_batch_noalloc: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int mpwsd_decode_batch_noalloc(const mpwsd_segment* segs, int nseg, int L, int T, int32_t* stats,
+                                          hipStream_t stream)
+{
+    mpwsd::clear_error();
+    int rc = validate(segs, nseg, L, T, true);
+    if (rc != MPWSD_OK) return rc;
+    size_t need = 0;
+    for (int i = 0; i < nseg; ++i) need += carve(segs[i], L, T, nullptr).bytes;
+    if (need > kNoallocScratchBytes)
+        return mpwsd::fail(MPWSD_ERR_SIZE,
+                           "mpwsd_decode_batch_noalloc: these segments need %zu bytes of workspace, above the fixed "
+                           "%zu (use mpwsd_decode_batch with a workspace of its size)",
+                           need, kNoallocScratchBytes);
+    void* ws = scratch_ptr();
+    if (!ws) return MPWSD_ERR_DEVICE;
+    return decode(segs, nseg, L, T, ws, kNoallocScratchBytes, stats, nullptr, stream);
 }
 
 extern "C" int mpwsd_decode_batch_ex(const mpwsd_segment* segs, int nseg, int L, int T, void* ws, size_t ws_bytes,

@@ -18,6 +18,7 @@ def test_library_exports_every_declared_call():
                           "mpwsd_quantize_llr",
                           "mpwsd_stage1_osd",
                           "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
+                          "mpwsd_decode_batch_noalloc",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
                           "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy",
                           "mpwsd_server_arena_bytes", "mpwsd_server_create", "mpwsd_server_submit",
