@@ -1,7 +1,7 @@
 """Serving: a continuous-batching server over the C-ABI and a trace-driven
 load test (Poisson arrivals of frames of several codes).
 
-    python -m paper_2602_08501_amd.serve --rate 1e5 3e5 1e6 --seconds 1.0
+    python -m paper_2602_08501_amd.serve --rate 1e5 3e5 1e6 --seconds 10
 
 Codes RM(2,7) / RM(3,7) / RM(3,8) in equal shares, Eb/N0 uniform in
 [1.5, 3.5] dB per frame, int8 LLRs, up to 8192 frames of each code in flight
@@ -131,7 +131,7 @@ def make_trace(rate: float, seconds: float, rows: int, seed: int = 9):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rate", type=float, nargs="+", default=[1e5, 3e5, 1e6])
-    ap.add_argument("--seconds", type=float, default=1.0)
+    ap.add_argument("--seconds", type=float, default=10.0)
     ap.add_argument("--rows", type=int, default=16384, help="distinct frames per code in the pool")
     ap.add_argument("--capacity", type=int, default=8192)
     args = ap.parse_args()
