@@ -1,7 +1,8 @@
 """Benchmark: decoded frames/s of the two-stage MP-WSD decoder on one GPU.
 
 One step = the whole decoder over one batch resident in HBM: int8 LLR
-quantization, stage-1 SC-list decoding with the CRC test, compaction of the
+quantization and stage-1 SC-list decoding with the CRC test (one launch;
+quantization on its own before OSD), compaction of the
 failing frames, T iterations of the stage-2 move search / apply, and the
 final choice.  The step is recorded once as a HIP graph and replayed.
 
@@ -174,10 +175,12 @@ def main():
     def stage1_all(raw=None):
         for i, (wl, F) in enumerate(segs):
             kw = {"stream": stream} if raw is None else {"raw_stream": raw}
-            D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], **kw)
             if osd is None:
-                D.stage1(codes[i], L, q_d[i], wl.crc_len, wl.crc_poly, out=s1[i], **kw)
+                # quantizer and SCL in one launch (the int8 values also go to q_d for stage 2)
+                D.stage1_quantized(codes[i], L, y_d[i], float(wl.llr_scale), wl.crc_len, wl.crc_poly, q=q_d[i],
+                                   out=s1[i], **kw)
             else:
+                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], **kw)
                 D.stage1_osd(codes[i], osd, L, q_d[i], out=s1[i], **kw)
 
     # OSD has no CRC: stage 2 runs on every frame (always-on mode)

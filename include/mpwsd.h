@@ -148,6 +148,24 @@ int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L,
                      hipStream_t stream);
 
 /*
+ * mpwsd_stage1_scl_quantized - the int8 stage 1 from received values:
+ * mpwsd_quantize_llr(y, F N, scale, q, bad) followed by
+ * mpwsd_stage1_scl(r, m, crc_len, crc_poly, L, q, MPWSD_I8, F, ...), with
+ * the same outputs bit for bit, in one launch when y is 16-byte and q 4-byte
+ * aligned (each wave quantizes the values it decodes and writes them to q
+ * for stage 2), else as those two launches.
+ *
+ * y: device float [F][N]; scale: finite; q: device out int8 [F][N];
+ * bad: device int32 counter of non-finite y (those give q = 0), or NULL.
+ * Other arguments, outputs, supported range and errors as mpwsd_stage1_scl
+ * (Sec. III-A), plus MPWSD_ERR_ARG for a non-finite scale or a null y / q.
+ */
+int mpwsd_stage1_scl_quantized(int r, int m, int crc_len, uint32_t crc_poly, int L,
+                               const float* y, float scale, int64_t F, int8_t* q, int32_t* bad,
+                               uint8_t* anchors, uint8_t* crc_ok, int32_t* pm,
+                               hipStream_t stream);
+
+/*
  * mpwsd_stage1_osd - stage 1 by ordered-statistics decoding of order k
  * (Sec. III-A; the OSD initialisation of Sec. IV-A, whose complexity is
  * sum_{i<=k} C(K, i) candidates, Table I).  No CRC is involved: stage 2 then

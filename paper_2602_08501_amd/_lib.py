@@ -80,6 +80,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_quantize_llr.argtypes = [_p, _i64, _f, _p, _p, _p]
         lib.mpwsd_stage1_scl.argtypes = [_i, _i, _i, _u32, _i, _p, _i, _i64, _p, _p, _p, _p]
         lib.mpwsd_stage1_osd.argtypes = [_i, _i, _i, _i, _p, _i, _i64, _p, _p, _p]
+        lib.mpwsd_stage1_scl_quantized.argtypes = [_i, _i, _i, _u32, _i, _p, _f, _i64, _p, _p, _p, _p, _p, _p]
         lib.mpwsd_workspace_bytes.argtypes = [ctypes.POINTER(Segment), _i, _i, _i]
         lib.mpwsd_workspace_bytes.restype = _sz
         lib.mpwsd_decode_batch.argtypes = [ctypes.POINTER(Segment), _i, _i, _i, _p, _sz, _p, _p]
@@ -100,7 +101,7 @@ def load() -> ctypes.CDLL:
         lib.mpwsd_server_destroy.argtypes = [_p]
         lib.mpwsd_serve_trace.argtypes = [_p, _i64, _p, _p, _p, _p, ctypes.POINTER(_p), ctypes.POINTER(Result)]
         for name in ("mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_group_moves", "mpwsd_quantize_llr",
-                     "mpwsd_stage1_scl", "mpwsd_stage1_osd", "mpwsd_decode_batch",
+                     "mpwsd_stage1_scl", "mpwsd_stage1_scl_quantized", "mpwsd_stage1_osd", "mpwsd_decode_batch",
                      "mpwsd_decode_batch_noalloc", "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin", "mpwsd_graph_end",
                      "mpwsd_graph_launch", "mpwsd_graph_destroy", "mpwsd_server_create", "mpwsd_server_submit",
                      "mpwsd_server_tick", "mpwsd_server_poll", "mpwsd_server_destroy", "mpwsd_serve_trace"):
@@ -158,6 +159,12 @@ def mpwsd_stage1_scl(r, m, crc_len, crc_poly, L, llr_ptr, dtype, F, anchors_ptr,
                      pm_ptr, stream) -> int:
     return load().mpwsd_stage1_scl(r, m, crc_len, crc_poly, L, llr_ptr, dtype, F, anchors_ptr,
                                    crc_ok_ptr, pm_ptr, stream)
+
+
+def mpwsd_stage1_scl_quantized(r, m, crc_len, crc_poly, L, y_ptr, scale, F, q_ptr, bad_ptr, anchors_ptr,
+                               crc_ok_ptr, pm_ptr, stream) -> int:
+    return load().mpwsd_stage1_scl_quantized(r, m, crc_len, crc_poly, L, y_ptr, scale, F, q_ptr, bad_ptr,
+                                             anchors_ptr, crc_ok_ptr, pm_ptr, stream)
 
 
 def mpwsd_stage1_osd(r, m, order, L, llr_ptr, dtype, F, anchors_ptr, metric_ptr, stream) -> int:

@@ -559,13 +559,36 @@ template <int M, int L, bool FLOAT> struct Scl {
     }
 };
 
-template <int M, int L, bool FLOAT>
+// q = clamp(round_half_even(fl32(v s)), -127, 127); a non-finite v gives 0
+// and is counted in *bad.
+__device__ inline uint32_t quantize1(float v, float s, int32_t* __restrict__ bad)
+{
+    if (!isfinite(v)) {
+        if (bad) atomicAdd(bad, 1);
+        return 0u;
+    }
+    float t = rintf(__fmul_rn(v, s));  // a product overflowing to +-inf clamps below
+    t = fminf(fmaxf(t, -127.0f), 127.0f);
+    return (uint32_t)(uint8_t)(int8_t)t;
+}
+
+// The quantizer inside the SCL launch (QUANT): llr is float y, 16-byte
+// aligned; q receives the int8 values (4-byte aligned), bad counts non-finite
+// inputs.
+struct QuantArgs {
+    float scale;
+    int8_t* q;
+    int32_t* bad;
+};
+
+template <int M, int L, bool FLOAT, bool QUANT = false>
 __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr, int64_t F,
                                                    uint64_t info0, uint64_t info1, uint64_t info2, uint64_t info3,
                                                    int crc_len, CrcRows crc, Sched sched,
                                                    uint8_t* __restrict__ anchors, uint8_t* __restrict__ crc_ok,
-                                                   int32_t* __restrict__ pm_out)
+                                                   int32_t* __restrict__ pm_out, QuantArgs qa)
 {
+    static_assert(!(QUANT && FLOAT), "the quantizer feeds the int8 form");
     using K = Scl<M, L, FLOAT>;
     using A = typename K::A;
     using V = typename K::V;
@@ -584,7 +607,23 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     // stage the channel values of the wave's frames (coalesced); int8 q four
     // values per lane and load when it is 4-byte aligned, widened to two
     // int16 pairs (a frame's N values never share a word with another frame)
-    if (!FLOAT && (reinterpret_cast<uintptr_t>(llr) & 3u) == 0) {
+    if constexpr (QUANT) {
+        // four values per lane: one 16-byte load of y, one 4-byte store of q
+        for (int e = 4 * lane; e < G * N; e += 4 * WAVE) {
+            const int64_t fr = (int64_t)blockIdx.x * G + e / N;
+            uint32_t w = 0u;
+            if (fr < F) {
+                const float4 v = *reinterpret_cast<const float4*>((const float*)llr + fr * N + e % N);
+                w = quantize1(v.x, qa.scale, qa.bad) | (quantize1(v.y, qa.scale, qa.bad) << 8) |
+                    (quantize1(v.z, qa.scale, qa.bad) << 16) | (quantize1(v.w, qa.scale, qa.bad) << 24);
+                *reinterpret_cast<uint32_t*>(qa.q + fr * N + e % N) = w;
+            }
+            auto wide = [](uint32_t b) { return (uint32_t)(uint16_t)(int16_t)(int8_t)(uint8_t)b; };
+            uint32_t* d = reinterpret_cast<uint32_t*>(sm.ch + (e / N) * K::CHS + e % N);
+            d[0] = wide(w) | (wide(w >> 8) << 16);
+            d[1] = wide(w >> 16) | (wide(w >> 24) << 16);
+        }
+    } else if (!FLOAT && (reinterpret_cast<uintptr_t>(llr) & 3u) == 0) {
         for (int e = 4 * lane; e < G * N; e += 4 * WAVE) {
             const int64_t fr = (int64_t)blockIdx.x * G + e / N;
             const uint32_t w =
@@ -707,16 +746,6 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     }
 }
 
-__device__ inline uint32_t quantize1(float v, float s, int32_t* __restrict__ bad)
-{
-    if (!isfinite(v)) {
-        if (bad) atomicAdd(bad, 1);
-        return 0u;
-    }
-    float t = rintf(__fmul_rn(v, s));  // a product overflowing to +-inf clamps below
-    t = fminf(fmaxf(t, -127.0f), 127.0f);
-    return (uint32_t)(uint8_t)(int8_t)t;
-}
 
 __global__ void quantize_kernel(const float* __restrict__ y, int64_t n, float s, int8_t* __restrict__ q,
                                 int32_t* __restrict__ bad)
@@ -788,26 +817,34 @@ CrcRows make_crc_rows(int m, const uint64_t* info, int crc_len, uint32_t poly)
 
 template <int M, int L, bool FL>
 void launch_scl3(const void* llr, int64_t F, const uint64_t* info, int crc_len, uint32_t poly, uint8_t* anchors,
-                 uint8_t* crc_ok, int32_t* pm, hipStream_t s)
+                 uint8_t* crc_ok, int32_t* pm, const QuantArgs* qa, hipStream_t s)
 {
     constexpr int64_t per = WAVE / L;
     const int64_t blocks = (F + per - 1) / per;
+    if constexpr (!FL) {
+        if (qa) {
+            hipLaunchKernelGGL((scl_kernel<M, L, false, true>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F,
+                               info[0], info[1], info[2], info[3], crc_len, make_crc_rows(M, info, crc_len, poly),
+                               make_sched(M, info), anchors, crc_ok, pm, *qa);
+            return;
+        }
+    }
     hipLaunchKernelGGL((scl_kernel<M, L, FL>), dim3((unsigned)blocks), dim3(WAVE), 0, s, llr, F, info[0], info[1],
                        info[2], info[3], crc_len, make_crc_rows(M, info, crc_len, poly), make_sched(M, info), anchors,
-                       crc_ok, pm);
+                       crc_ok, pm, QuantArgs{0.0f, nullptr, nullptr});
 }
 
 template <int M, bool FL>
 void launch_scl(const void* llr, int64_t F, int L, const uint64_t* info, int crc_len, uint32_t poly,
-                uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, hipStream_t s)
+                uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, const QuantArgs* qa, hipStream_t s)
 {
     switch (L) {
-    case 1: launch_scl3<M, 1, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
-    case 2: launch_scl3<M, 2, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
-    case 4: launch_scl3<M, 4, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
-    case 8: launch_scl3<M, 8, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
-    case 16: launch_scl3<M, 16, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
-    default: launch_scl3<M, 32, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, s); break;
+    case 1: launch_scl3<M, 1, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
+    case 2: launch_scl3<M, 2, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
+    case 4: launch_scl3<M, 4, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
+    case 8: launch_scl3<M, 8, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
+    case 16: launch_scl3<M, 16, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
+    default: launch_scl3<M, 32, FL>(llr, F, info, crc_len, poly, anchors, crc_ok, pm, qa, s); break;
     }
 }
 
@@ -839,43 +876,87 @@ extern "C" int mpwsd_quantize_llr(const float* y, int64_t n, float scale, int8_t
     return MPWSD_OK;
 }
 
+namespace {
+// Argument checks shared by the SCL entry points (nothing enqueued on error).
+int scl_check(const char* fn, int r, int m, int crc_len, uint32_t crc_poly, int L, int64_t F)
+{
+    using namespace mpwsd;
+    if (m < 5 || m > 8 || r < 1 || r >= m)
+        return fail(MPWSD_ERR_UNSUPPORTED, "%s: need 1 <= r < m, 5 <= m <= 8 (r=%d m=%d)", fn, r, m);
+    const int K = rm_dimension(r, m);
+    if (L < 1 || L > 32 || (L & (L - 1)) != 0)
+        return fail(MPWSD_ERR_UNSUPPORTED, "%s: L must be a power of two <= 32 (L=%d)", fn, L);
+    if (K < 6 && L > (1 << K))
+        return fail(MPWSD_ERR_UNSUPPORTED, "%s: L=%d exceeds the code size 2^%d", fn, L, K);
+    if (crc_len < 0 || crc_len > 16 || crc_len > K)
+        return fail(MPWSD_ERR_UNSUPPORTED, "%s: crc_len must be in [0, min(16, K)] (got %d)", fn, crc_len);
+    if (crc_len > 0 && ((crc_poly >> crc_len) & 1u) == 0)
+        return fail(MPWSD_ERR_ARG, "%s: crc_poly must include the x^%d term", fn, crc_len);
+    if (F < 0) return fail(MPWSD_ERR_ARG, "%s: F < 0", fn);
+    return MPWSD_OK;
+}
+
+int scl_launch(const char* fn, int r, int m, int crc_len, uint32_t crc_poly, int L, const void* llr, bool fl,
+               int64_t F, uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, const QuantArgs* qa, hipStream_t stream)
+{
+    using namespace mpwsd;
+    uint64_t info[4] = {0, 0, 0, 0};
+    for (int i = 0; i < (1 << m); ++i)
+        if (__builtin_popcount((unsigned)i) >= m - r) info[i >> 6] |= 1ull << (i & 63);
+    switch (m) {
+    case 5: fl ? launch_scl<5, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream)
+               : launch_scl<5, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream); break;
+    case 6: fl ? launch_scl<6, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream)
+               : launch_scl<6, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream); break;
+    case 7: fl ? launch_scl<7, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream)
+               : launch_scl<7, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream); break;
+    default: fl ? launch_scl<8, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream)
+                : launch_scl<8, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, qa, stream); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(MPWSD_ERR_DEVICE, "%s: %s", fn, hipGetErrorString(e));
+    return MPWSD_OK;
+}
+}  // namespace
+
 extern "C" int mpwsd_stage1_scl(int r, int m, int crc_len, uint32_t crc_poly, int L, const void* llr, int dtype,
                                 int64_t F, uint8_t* anchors, uint8_t* crc_ok, int32_t* pm, hipStream_t stream)
 {
     using namespace mpwsd;
     clear_error();
-    if (m < 5 || m > 8 || r < 1 || r >= m)
-        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: need 1 <= r < m, 5 <= m <= 8 (r=%d m=%d)", r, m);
-    const int K = rm_dimension(r, m);
-    if (L < 1 || L > 32 || (L & (L - 1)) != 0)
-        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: L must be a power of two <= 32 (L=%d)", L);
-    if (K < 6 && L > (1 << K))
-        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: L=%d exceeds the code size 2^%d", L, K);
-    if (crc_len < 0 || crc_len > 16 || crc_len > K)
-        return fail(MPWSD_ERR_UNSUPPORTED, "mpwsd_stage1_scl: crc_len must be in [0, min(16, K)] (got %d)", crc_len);
-    if (crc_len > 0 && ((crc_poly >> crc_len) & 1u) == 0)
-        return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: crc_poly must include the x^%d term", crc_len);
+    const char* fn = "mpwsd_stage1_scl";
+    int rc = scl_check(fn, r, m, crc_len, crc_poly, L, F);
+    if (rc != MPWSD_OK) return rc;
     if (dtype != MPWSD_I8 && dtype != MPWSD_F32) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: bad dtype %d", dtype);
-    if (F < 0) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: F < 0");
     if (F == 0) return MPWSD_OK;
     if (!llr || !anchors || !crc_ok) return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: null pointer");
     if ((reinterpret_cast<uintptr_t>(anchors) & 3u) != 0)
         return fail(MPWSD_ERR_ARG, "mpwsd_stage1_scl: anchors must be 4-byte aligned");
-    uint64_t info[4] = {0, 0, 0, 0};
-    for (int i = 0; i < (1 << m); ++i)
-        if (__builtin_popcount((unsigned)i) >= m - r) info[i >> 6] |= 1ull << (i & 63);
-    const bool fl = dtype == MPWSD_F32;
-    switch (m) {
-    case 5: fl ? launch_scl<5, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
-               : launch_scl<5, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
-    case 6: fl ? launch_scl<6, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
-               : launch_scl<6, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
-    case 7: fl ? launch_scl<7, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
-               : launch_scl<7, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
-    default: fl ? launch_scl<8, true>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream)
-                : launch_scl<8, false>(llr, F, L, info, crc_len, crc_poly, anchors, crc_ok, pm, stream); break;
+    return scl_launch(fn, r, m, crc_len, crc_poly, L, llr, dtype == MPWSD_F32, F, anchors, crc_ok, pm, nullptr,
+                      stream);
+}
+
+extern "C" int mpwsd_stage1_scl_quantized(int r, int m, int crc_len, uint32_t crc_poly, int L, const float* y,
+                                          float scale, int64_t F, int8_t* q, int32_t* bad, uint8_t* anchors,
+                                          uint8_t* crc_ok, int32_t* pm, hipStream_t stream)
+{
+    using namespace mpwsd;
+    clear_error();
+    const char* fn = "mpwsd_stage1_scl_quantized";
+    int rc = scl_check(fn, r, m, crc_len, crc_poly, L, F);
+    if (rc != MPWSD_OK) return rc;
+    if (!std::isfinite(scale)) return fail(MPWSD_ERR_ARG, "%s: scale must be finite", fn);
+    if (F == 0) return MPWSD_OK;
+    if (!y || !q || !anchors || !crc_ok) return fail(MPWSD_ERR_ARG, "%s: null pointer", fn);
+    if ((reinterpret_cast<uintptr_t>(anchors) & 3u) != 0) return fail(MPWSD_ERR_ARG, "%s: anchors must be 4-byte aligned", fn);
+    if ((reinterpret_cast<uintptr_t>(y) & 15u) != 0 || (reinterpret_cast<uintptr_t>(q) & 3u) != 0) {
+        // the fused launch reads y 16 bytes and writes q 4 bytes at a time: the
+        // same two steps as separate launches otherwise
+        rc = mpwsd_quantize_llr(y, F << m, scale, q, bad, stream);
+        if (rc != MPWSD_OK) return rc;
+        clear_error();
+        return scl_launch(fn, r, m, crc_len, crc_poly, L, q, false, F, anchors, crc_ok, pm, nullptr, stream);
     }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(MPWSD_ERR_DEVICE, "mpwsd_stage1_scl: %s", hipGetErrorString(e));
-    return MPWSD_OK;
+    const QuantArgs qa{scale, q, bad};
+    return scl_launch(fn, r, m, crc_len, crc_poly, L, y, false, F, anchors, crc_ok, pm, &qa, stream);
 }

@@ -131,6 +131,28 @@ def stage1(code: Code, L: int, llr: torch.Tensor, crc_len: int = 6, crc_poly: in
     return out
 
 
+def stage1_quantized(code: Code, L: int, y: torch.Tensor, scale: float, crc_len: int = 6, crc_poly: int = 0x43,
+                     q: torch.Tensor | None = None, bad: torch.Tensor | None = None, out=None, stream=None,
+                     want_pm: bool = False, raw_stream=None):
+    """quantize() then stage1() on the int8 values, in one launch: returns
+    the stage-1 outputs with the quantized values under "q"."""
+    F = y.shape[0]
+    dev = y.device
+    if out is None:
+        out = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
+               "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)}
+        if want_pm:
+            out["pm"] = torch.empty((F, L), dtype=torch.int32, device=dev)
+    if q is None:
+        q = torch.empty(y.shape, dtype=torch.int8, device=dev)
+    out["q"] = q
+    check(_lib.mpwsd_stage1_scl_quantized(code.r, code.m, crc_len, crc_poly, L, y.data_ptr(),
+                                          float(np.float32(scale)), F, q.data_ptr(), _ptr(bad),
+                                          out["anchors"].data_ptr(), out["crc_ok"].data_ptr(), _ptr(out.get("pm")),
+                                          raw_stream if raw_stream is not None else _stream(stream)))
+    return out
+
+
 def stage1_osd(code: Code, order: int, L: int, llr: torch.Tensor, out=None, stream=None, want_metric: bool = False,
                raw_stream=None):
     """OSD(order) anchors of every frame, smallest metric first (no CRC: run

@@ -17,7 +17,8 @@ def test_library_exports_every_declared_call():
     assert set(names) == {"mpwsd_last_error", "mpwsd_build_moves", "mpwsd_build_sphere", "mpwsd_group_moves",
                           "mpwsd_quantize_llr",
                           "mpwsd_stage1_osd",
-                          "mpwsd_stage1_scl", "mpwsd_workspace_bytes", "mpwsd_decode_batch",
+                          "mpwsd_stage1_scl", "mpwsd_stage1_scl_quantized", "mpwsd_workspace_bytes",
+                          "mpwsd_decode_batch",
                           "mpwsd_decode_batch_noalloc",
                           "mpwsd_decode_batch_ex", "mpwsd_search_variants", "mpwsd_graph_begin",
                           "mpwsd_graph_end", "mpwsd_graph_launch", "mpwsd_graph_destroy",
@@ -167,6 +168,33 @@ def test_stage1_validates_before_enqueue():
     assert _lib.mpwsd_quantize_llr(None, 0, 1.0, None, None, None) == 0
     assert _lib.mpwsd_quantize_llr(None, 5, 1.0, None, None, None) == _lib.MPWSD_ERR_ARG
     assert _lib.mpwsd_quantize_llr(A, 5, float("inf"), A, None, None) == _lib.MPWSD_ERR_ARG
+
+
+def test_stage1_quantized_validates_before_enqueue():
+    A = 0x1000
+    cases = [
+        (dict(r=3, m=9), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(L=6), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(crc_len=17), _lib.MPWSD_ERR_UNSUPPORTED),
+        (dict(crc_poly=0x03), _lib.MPWSD_ERR_ARG),
+        (dict(scale=float("nan")), _lib.MPWSD_ERR_ARG),
+        (dict(F=-2), _lib.MPWSD_ERR_ARG),
+        (dict(y=None), _lib.MPWSD_ERR_ARG),
+        (dict(q=None), _lib.MPWSD_ERR_ARG),
+        (dict(anchors=None), _lib.MPWSD_ERR_ARG),
+        (dict(anchors=A + 2), _lib.MPWSD_ERR_ARG),
+    ]
+    for kw, code in cases:
+        a = dict(r=3, m=7, crc_len=6, crc_poly=0x43, L=8, y=A, scale=12.9, F=4, q=A, bad=None, anchors=A, crc_ok=A,
+                 pm=None, stream=None)
+        a.update(kw)
+        rc = _lib.mpwsd_stage1_scl_quantized(a["r"], a["m"], a["crc_len"], a["crc_poly"], a["L"], a["y"],
+                                             a["scale"], a["F"], a["q"], a["bad"], a["anchors"], a["crc_ok"],
+                                             a["pm"], a["stream"])
+        assert rc == code, (kw, _lib.last_error())
+        assert "quantized" in _lib.last_error()
+    assert _lib.mpwsd_stage1_scl_quantized(3, 7, 6, 0x43, 8, None, 1.0, 0, None, None, None, None, None,
+                                           None) == 0
 
 
 def test_search_variants_and_option_errors():

@@ -86,6 +86,40 @@ def test_quantizer_parity_and_nonfinite():
 
 
 # ---------------------------------------------------------------- stage 1
+@pytest.mark.parametrize("wl,L,F", [(synth.RM37, 8, 640), (synth.RM38, 16, 40), (synth.RM26, 4, 333),
+                                    (synth.RM27, 32, 24)])
+@pytest.mark.parametrize("offset", [0, 1])
+def test_stage1_quantized_equals_quantize_then_scl(wl, L, F, offset):
+    """mpwsd_stage1_scl_quantized against mpwsd_quantize_llr + mpwsd_stage1_scl
+    (int8): the fused launch for aligned buffers, the two-launch form for y and
+    q one element off alignment; non-finite values included."""
+    say("case: stage1 quantized", wl, L, F, "offset", offset)
+    c, y, q_ref = workload(wl, 3, F)
+    y = y.copy()
+    y[1, [3, 77 % y.shape[1]]] = [np.nan, np.inf]
+    y[F - 1, 5] = -np.inf
+    n = y.size
+    ybuf = torch.zeros(n + 8, dtype=torch.float32, device=DEV)
+    ybuf[offset:offset + n] = torch.from_numpy(y.ravel()).to(DEV)
+    yd = ybuf[offset:offset + n].view(y.shape)
+    qbuf = torch.full((n + 8,), 99, dtype=torch.int8, device=DEV)
+    qd = qbuf[offset:offset + n].view(y.shape)
+    cd = code(wl.r, wl.m)
+    bad = torch.zeros(1, dtype=torch.int32, device=DEV)
+    got = D.stage1_quantized(cd, L, yd, wl.llr_scale, wl.crc_len, wl.crc_poly, q=qd, bad=bad, want_pm=True)
+    bad2 = torch.zeros(1, dtype=torch.int32, device=DEV)
+    q2 = D.quantize(yd.contiguous(), wl.llr_scale, bad2)
+    ref = D.stage1(cd, L, q2, wl.crc_len, wl.crc_poly, want_pm=True)
+    torch.cuda.synchronize()
+    # non-finite values quantize to 0 (and are counted)
+    assert np.array_equal(qd.cpu().numpy(), oracle.quantize(np.where(np.isfinite(y), y, 0.0), wl.llr_scale))
+    assert np.array_equal(qd.cpu().numpy(), q2.cpu().numpy())
+    assert bad.item() == bad2.item() == 3
+    assert (qbuf[:offset] == 99).all() and (qbuf[offset + n:] == 99).all()
+    for k in ("anchors", "crc_ok", "pm"):
+        assert np.array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy()), k
+
+
 # the last two: a 16-bit CRC (x^16 + x^12 + x^5 + 1) and an 11-bit one (x^11 + x^10 + x^9 + x^5 + 1)
 # whose test rows span every word of the decided bits
 CRC16_RM37 = dataclasses.replace(synth.RM37, k_pay=48, crc_len=16, crc_poly=0x11021)
