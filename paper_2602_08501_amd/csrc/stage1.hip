@@ -644,7 +644,7 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
     V pm = 0;
     bool valid = (slot == 0);
     uint64_t ptrs = 0;  // byte l: group slot owning this path's level-l buffer
-    const uint32_t dirs = K::template bitonic_dirs<2>(slot);  // sorting-network directions of this lane
+    const uint32_t dirs = FLOAT ? K::template bitonic_dirs<2>(slot) : 0u;  // sorting-network directions of this lane
     const uint32_t fdirs = FLOAT ? 0u : K::one_key_dirs(slot);
     // the slots hold the paths in ascending (PM, index) order; a frozen leaf
     // adds penalties path by path and breaks that order until the next sort
@@ -695,6 +695,17 @@ __global__ __launch_bounds__(WAVE) void scl_kernel(const void* __restrict__ llr,
             const Key b = K::make_key(valid, (V)(pm + (lam < 0 ? -lam : lam)), 2 * slot + 1 - zb);
             const Key bd = (Key)K::template sort1<2, 1, 0>((uint32_t)b, fdirs);
             mine = (Key)K::template merge1<L / 2, K::NSORT1>((uint32_t)(a < bd ? a : bd), fdirs);
+        } else if constexpr (!FLOAT) {
+            // both children may be penalised (a repetition node, or a leaf
+            // after a frozen one reordered the PMs): the bit-0 keys are sorted
+            // descending and the bit-1 keys ascending by the same networks with
+            // opposite directions, then the lane-wise minimum and one bitonic
+            // merge as above
+            const Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
+            const Key x1 = K::make_key(valid, (V)(pm + d1), 2 * slot + 1);
+            const Key xd = (Key)K::template sort1<2, 1, 0>((uint32_t)x0, fdirs);
+            const Key xa = (Key)K::template sort1<2, 1, 0>((uint32_t)x1, fdirs ^ ((1u << K::NSORT1) - 1u));
+            mine = (Key)K::template merge1<L / 2, K::NSORT1>((uint32_t)(xa < xd ? xa : xd), fdirs);
         } else {
             // all 2L children (two keys per lane) through a bitonic sort
             Key x0 = K::make_key(valid, (V)(pm + d0), 2 * slot);
