@@ -1,6 +1,6 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (whole step recorded as a HIP graph, autotuned search tiles, and for
-RM(3,7) also without move logs, as bench.py runs it), checked
+times (whole step recorded as a HIP graph, autotuned search tiles, and
+also without move logs, as bench.py runs it), checked
 against the oracle on sampled frames (every frame is decoded independently,
 so the oracle decodes the sampled rows alone)."""
 import dataclasses
@@ -26,9 +26,10 @@ def say(*a):
 
 
 def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None):
-    """The step bench.py times: quantize, stage 1 and stage 2 recorded as one
-    HIP graph with autotuned per-iteration tiles (or the given ones), replayed
-    twice.  bench.py itself runs it with want_moves=False (no move logs)."""
+    """The step bench.py times: quantizer + stage 1 (one launch) and stage 2
+    recorded as one HIP graph with autotuned per-iteration tiles (or the given
+    ones), replayed twice.  bench.py itself runs it with want_moves=False (no
+    move logs)."""
     pay, c, y = synth.generate(wl, seed, 0, F)
     code = D.Code(wl.r, wl.m, DEV)
     y_d = torch.from_numpy(y).to(DEV)
@@ -37,8 +38,7 @@ def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None):
           "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)}
     st = D.Stage2([(code, F)], L, T, "i8", DEV, want_moves=want_moves)
     scale = float(wl.llr_scale)
-    D.quantize(y_d, scale, out=q)
-    D.stage1(code, L, q, wl.crc_len, wl.crc_poly, out=s1)
+    D.stage1_quantized(code, L, y_d, scale, wl.crc_len, wl.crc_poly, q=q, out=s1)
     torch.cuda.synchronize()
     if tiles is None:
         variant, bpc = autotune.tune(st, [q], [s1["anchors"]], [s1["crc_ok"]], reps=1, use_cache=False)
@@ -46,8 +46,7 @@ def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None):
         variant, bpc = tiles
 
     def record(raw):
-        D.quantize(y_d, scale, out=q, raw_stream=raw)
-        D.stage1(code, L, q, wl.crc_len, wl.crc_poly, out=s1, raw_stream=raw)
+        D.stage1_quantized(code, L, y_d, scale, wl.crc_len, wl.crc_poly, q=q, out=s1, raw_stream=raw)
         st.run([q], [s1["anchors"]], [s1["crc_ok"]], variant=variant, blocks_per_cu=bpc, raw_stream=raw)
 
     g = D.Graph(record)
@@ -117,3 +116,9 @@ def test_rm38_config_size():
     rows = np.sort(np.concatenate([rng.choice(fail, 6, replace=False),
                                    rng.choice(np.nonzero(out["crc_ok"])[0], 10, replace=False)]))
     check_sample(wl, L, T, out, rows)
+    # as bench.py --workload rm38 times it: the same graph without move logs
+    say("case: RM(3,8) 32768 frames, bench configuration (no move logs)")
+    c2, y2, out2, stats2, _ = run_pipeline(wl, F, L, T, 0, want_moves=False, tiles=tiles)
+    for k in ("cw", "k", "metric", "crc_ok", "anchors", "q"):
+        assert np.array_equal(out2[k], out[k]), k
+    assert np.array_equal(stats2, stats)

@@ -119,8 +119,7 @@ def test_mixed_full_size_config():
     def stage1_all(raw=None):
         for (wl, code, q, s1, c), y, qq, ss in zip(segs, ys, qs, s1s):
             kw = {} if raw is None else {"raw_stream": raw}
-            D.quantize(y, float(wl.llr_scale), out=qq, **kw)
-            D.stage1(code, L, qq, wl.crc_len, wl.crc_poly, out=ss, **kw)
+            D.stage1_quantized(code, L, y, float(wl.llr_scale), wl.crc_len, wl.crc_poly, q=qq, out=ss, **kw)
 
     stage1_all()
     torch.cuda.synchronize()
