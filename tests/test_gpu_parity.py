@@ -179,6 +179,8 @@ E2E = [
     ("rm37_2dB", dataclasses.replace(synth.RM37, ebn0_db=2.0), 8, 8, 384),
     ("rm27", dataclasses.replace(synth.RM27, ebn0_db=2.0), 8, 8, 192),
     ("rm37_T1_L2", dataclasses.replace(synth.RM37, ebn0_db=1.5), 2, 1, 128),
+    # the largest list and iteration count the library takes (L = 32, T = 64)
+    ("rm26_L32_T64", dataclasses.replace(synth.RM26, ebn0_db=1.0), 32, 64, 80),
 ]
 
 
