@@ -45,17 +45,22 @@ def _save(d: dict) -> None:
         pass
 
 
-def candidates(N: int, multi: bool = False):
+def candidates(N: int, multi: bool = False, grouped: bool = False):
     """(variant, workgroups per CU) pairs to time; a batch of several codes
-    is searched by one launch that exists for the first three variants."""
+    is searched by one launch that exists for the first three variants.  The
+    workgroups per CU go up to what the 160 KB of LDS of a CU holds: the
+    plain search stages two 128-row chunks of N + 16 bytes per row, the
+    paired-half search three chunks of N/2-byte rows and eight chunks'
+    indices."""
     vs = _lib.mpwsd_search_variants()
     if multi:
         vs = vs[:3]
     kp = max(N, 64)
-    lds_fit = (160 * 1024) // (2 * 128 * (kp + 16))
+    lds = 3 * 128 * (N // 2) + 8 * 2 * 128 * 4 if grouped and not multi else 2 * 128 * (kp + 16)
+    lds_fit = (160 * 1024) // lds
     out = []
     for i, v in enumerate(vs):
-        for bpc in sorted({v["blocks_per_cu"], 1, 2, 3, 4}):
+        for bpc in sorted({v["blocks_per_cu"], 1, 2, 3, 4, 5, 6}):
             if 1 <= bpc <= lds_fit:
                 out.append((i, bpc))
     return out
@@ -77,7 +82,8 @@ def tune(stage2, llrs, anchors, crc_oks, reps: int = 3, stream=None, use_cache: 
         e.record(stream)
     ref = None
     results = []  # (variant, bpc, [ms per iteration])
-    for var, bpc in candidates(max(c.N for c, _ in stage2.codes_F), multi):
+    grouped = all(c.grouped is not None for c, _ in stage2.codes_F)
+    for var, bpc in candidates(max(c.N for c, _ in stage2.codes_F), multi, grouped):
         per_iter = None
         for r in range(reps + 1):
             stage2.run(llrs, anchors, crc_oks, stream=stream, events=events, variant=var, blocks_per_cu=bpc)

@@ -1377,7 +1377,7 @@ __global__ void select_kernel(const void* __restrict__ llr, const int32_t* __res
 struct Variant {
     int nc, nw, bpc;
 };
-constexpr Variant kVariants[] = {{8, 4, 2}, {4, 4, 4}, {4, 8, 2}, {8, 2, 4}, {2, 4, 4}};
+constexpr Variant kVariants[] = {{8, 4, 2}, {4, 4, 4}, {4, 8, 2}, {8, 2, 4}, {2, 4, 4}, {3, 4, 4}};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 int default_variant(int N) { return N >= 256 ? 1 : 0; }
@@ -1412,7 +1412,8 @@ void launch_search_pw_n(const int8_t* zneg, const PwTable& g, const int32_t* act
     case 1: launch_search_pw_v<N, 1>(zneg, g, act, count, keys, s, grid); break;
     case 2: launch_search_pw_v<N, 2>(zneg, g, act, count, keys, s, grid); break;
     case 3: launch_search_pw_v<N, 3>(zneg, g, act, count, keys, s, grid); break;
-    default: launch_search_pw_v<N, 4>(zneg, g, act, count, keys, s, grid); break;
+    case 4: launch_search_pw_v<N, 4>(zneg, g, act, count, keys, s, grid); break;
+    default: launch_search_pw_v<N, 5>(zneg, g, act, count, keys, s, grid); break;
     }
 }
 
@@ -1426,7 +1427,8 @@ void launch_search_i8_n(const int8_t* zneg, const uint8_t* moves, int64_t P, con
     case 1: launch_search_i8_v<N, 1>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
     case 2: launch_search_i8_v<N, 2>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
     case 3: launch_search_i8_v<N, 3>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
-    default: launch_search_i8_v<N, 4>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    case 4: launch_search_i8_v<N, 4>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
+    default: launch_search_i8_v<N, 5>(zneg, moves, P, act, count, keys, s, grid, pmap, pmap_pad); break;
     }
 }
 
