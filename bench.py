@@ -4,7 +4,14 @@ One step = the whole decoder over one batch resident in HBM: int8 LLR
 quantization and stage-1 SC-list decoding with the CRC test (one launch;
 quantization on its own before OSD), compaction of the
 failing frames, T iterations of the stage-2 move search / apply, and the
-final choice.  The step is recorded once as a HIP graph and replayed.
+final choice.  The step is recorded once as a HIP graph and replayed.  By
+default three batches are in flight: each has its own buffers and its own
+graph on its own stream, and the steps are replayed round-robin, so that the
+GPU fills one batch's idle time (the small, latency-bound late stage-2
+launches) with another's work; the default 48 steps give every stream the
+same number of replays.  ms_per_step is the timed span over the K steps divided by K;
+ms_per_step_one_in_flight is the same with one batch at a time (one step's
+latency).  Afterwards every batch's outputs must equal the first batch's.
 
 Default workload (the metric's): RM(3,7) (N=128, K=64 = 58 payload + CRC-6),
 BPSK over AWGN at Eb/N0 = 2.5 dB, 65536 frames, int8 LLRs (scale 8/sigma^2),
@@ -49,8 +56,8 @@ MI355X_INT8_DENSE_TOPS = 5000.0  # AMD published dense int8 MFMA peak (TOP/s)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=48)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--workload", default="rm37", choices=["rm37", "rm38", "mixed", "rm26", "rm26s2", "rm27osd"])
     ap.add_argument("--osd-order", type=int, default=2, help="OSD order k of the rm27osd workload")
     ap.add_argument("--frames", type=int, default=0, help="override the workload's frame count")
@@ -60,6 +67,8 @@ def parse():
                     help="oracle sample size in frames on all cores, one eighth of it on one core (0 = skip; "
                          "default: up to 32768, 2048 for rm38)")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="batches decoded at once, each step's graph on its own stream (1 = one after another)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a reference dispatch of "
                          "known traffic for hardware counters)")
@@ -157,7 +166,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    codes, ys, txs, y_d, q_d, s1 = [], [], [], [], [], []
+    codes, ys, txs, y_d = [], [], [], []
     for wl, F in segs:
         pay, c_tx, y = synth.generate(wl, args.seed, 0, F)
         code = D.Code(wl.r, wl.m, dev, radius=radius)
@@ -165,56 +174,95 @@ def main():
         ys.append(y)
         txs.append(c_tx)
         y_d.append(torch.from_numpy(y).to(dev))
-        q_d.append(torch.empty(y.shape, dtype=torch.int8, device=dev))
-        s1.append({"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=dev),
-                   "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)})
     F_total = sum(F for _, F in segs)
-    st = D.Stage2([(c, F) for c, (_, F) in zip(codes, segs)], L, T, "i8", dev, want_moves=False)
     nseg = len(segs)
+    B = args.in_flight
+    if B < 1:
+        sys.exit("bench.py: --in-flight must be at least 1")
 
-    def stage1_all(raw=None):
-        for i, (wl, F) in enumerate(segs):
-            kw = {"stream": stream} if raw is None else {"raw_stream": raw}
-            if osd is None:
-                # quantizer and SCL in one launch (the int8 values also go to q_d for stage 2)
-                D.stage1_quantized(codes[i], L, y_d[i], float(wl.llr_scale), wl.crc_len, wl.crc_poly, q=q_d[i],
-                                   out=s1[i], **kw)
-            else:
-                D.quantize(y_d[i], float(wl.llr_scale), out=q_d[i], **kw)
-                D.stage1_osd(codes[i], osd, L, q_d[i], out=s1[i], **kw)
+    class Batch:
+        """The buffers of one batch in flight: int8 LLRs, stage-1 outputs and
+        the stage-2 outputs and workspace (the input y is shared, read-only)."""
 
-    # OSD has no CRC: stage 2 runs on every frame (always-on mode)
-    crc_oks = [None if osd is not None else s["crc_ok"] for s in s1]
+        def __init__(self):
+            self.q = [torch.empty(y.shape, dtype=torch.int8, device=dev) for y in ys]
+            self.s1 = [{"anchors": torch.empty((F, L, c.N // 8), dtype=torch.uint8, device=dev),
+                        "crc_ok": torch.empty(F, dtype=torch.uint8, device=dev)} for c, (_, F) in zip(codes, segs)]
+            self.st = D.Stage2([(c, F) for c, (_, F) in zip(codes, segs)], L, T, "i8", dev, want_moves=False)
+            # OSD has no CRC: stage 2 runs on every frame (always-on mode)
+            self.crc_oks = [None if osd is not None else s["crc_ok"] for s in self.s1]
+            self.anchors = [s["anchors"] for s in self.s1]
 
-    def stage2(events=None, variant=-1, bpc=0, raw=None):
-        st.run(q_d, [s["anchors"] for s in s1], crc_oks, stream=None if raw else stream,
-               events=events, variant=variant, blocks_per_cu=bpc, raw_stream=raw)
+        def stage1(self, raw=None):
+            for i, (wl, F) in enumerate(segs):
+                kw = {"stream": stream} if raw is None else {"raw_stream": raw}
+                if osd is None:
+                    # quantizer and SCL in one launch (the int8 values also go to q for stage 2)
+                    D.stage1_quantized(codes[i], L, y_d[i], float(wl.llr_scale), wl.crc_len, wl.crc_poly,
+                                       q=self.q[i], out=self.s1[i], **kw)
+                else:
+                    D.quantize(y_d[i], float(wl.llr_scale), out=self.q[i], **kw)
+                    D.stage1_osd(codes[i], osd, L, self.q[i], out=self.s1[i], **kw)
+
+        def stage2(self, events=None, variant=-1, bpc=0, raw=None):
+            self.st.run(self.q, self.anchors, self.crc_oks, stream=None if raw else stream,
+                        events=events, variant=variant, blocks_per_cu=bpc, raw_stream=raw)
+
+    batches = [Batch() for _ in range(B)]
+    b0 = batches[0]
+    st, q_d, s1, crc_oks = b0.st, b0.q, b0.s1, b0.crc_oks
 
     with torch.cuda.stream(stream):
-        stage1_all()
-        stage2()
+        b0.stage1()
+        b0.stage2()
         torch.cuda.synchronize()
-        variant, bpc = autotune.tune(st, q_d, [s["anchors"] for s in s1], crc_oks, stream=stream, use_cache=False)
+        variant, bpc = autotune.tune(st, q_d, b0.anchors, crc_oks, stream=stream, use_cache=False)
 
-        # the whole step recorded once as a HIP graph, replayed per step
-        def record(raw):
-            stage1_all(raw)
-            stage2(variant=variant, bpc=bpc, raw=raw)
+        # the whole step recorded once per batch in flight as a HIP graph; the
+        # steps are replayed round-robin on one stream per batch, so that up
+        # to B batches are decoded at once (the GPU fills the idle time of one
+        # batch's small late launches and launch gaps with another's work)
+        def record(b, raw):
+            b.stage1(raw)
+            b.stage2(variant=variant, bpc=bpc, raw=raw)
 
-        graph = D.Graph(record)
-        for _ in range(args.warmup):
-            graph.launch(stream)
+        graphs = [D.Graph(lambda raw, b=b: record(b, raw)) for b in batches]
+        streams = [stream] + [torch.cuda.Stream() for _ in range(B - 1)]
+
+        def timed(nb, steps):
+            """steps replays round-robin over the first nb batches; returns
+            ms per step between events that bracket every stream."""
+            torch.cuda.synchronize()
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(streams[0])
+            for s in streams[1:nb]:
+                s.wait_event(t0)
+            for k in range(steps):
+                graphs[k % nb].launch(streams[k % nb])
+            for s in streams[1:nb]:
+                e = torch.cuda.Event()
+                e.record(s)
+                streams[0].wait_event(e)
+            t1.record(streams[0])
+            torch.cuda.synchronize()
+            return t0.elapsed_time(t1) / steps
+
+        for k in range(args.warmup):
+            graphs[k % B].launch(streams[k % B])
         torch.cuda.synchronize()
-
-        t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         wall0 = time.perf_counter()
-        t_start.record(stream)
-        for k in range(args.steps):
-            graph.launch(stream)
-        t_end.record(stream)
-        torch.cuda.synchronize()
+        ms = timed(B, args.steps)
         wall = time.perf_counter() - wall0
-        ms = t_start.elapsed_time(t_end) / args.steps
+        # one batch at a time (the latency of one step)
+        ms_serial = timed(1, args.steps) if B > 1 else ms
+        # every batch in flight decoded the same frames: the same outputs
+        for b in batches[1:]:
+            for x, y in zip(b.st.outs, st.outs):
+                for k in x:
+                    assert torch.equal(x[k], y[k]), k
+            for x, y in zip(b.s1, s1):
+                for k in x:
+                    assert torch.equal(x[k], y[k]), k
 
         # the same steps launched one by one with HIP events around every
         # search launch (its durations for the roofline entry)
@@ -229,8 +277,8 @@ def main():
         e_start, e_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e_start.record(stream)
         for k in range(args.steps):
-            stage1_all()
-            stage2(evs[k], variant, bpc)
+            b0.stage1()
+            b0.stage2(evs[k], variant, bpc)
         e_end.record(stream)
         torch.cuda.synchronize()
         ms_eager = e_start.elapsed_time(e_end) / args.steps
@@ -285,6 +333,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "batches_in_flight": B,
+        "ms_per_step_one_in_flight": ms_serial,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -1,6 +1,6 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (whole step recorded as a HIP graph, autotuned search tiles, and
-also without move logs, as bench.py runs it), checked
+times (whole step recorded as a HIP graph, autotuned search tiles, without
+move logs, several batches in flight on their own streams), checked
 against the oracle on sampled frames (every frame is decoded independently,
 so the oracle decodes the sampled rows alone)."""
 import dataclasses
@@ -25,41 +25,66 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None):
+class Batch:
+    """The buffers of one batch: int8 LLRs, stage-1 outputs, stage-2 outputs
+    and workspace; the input y is shared."""
+
+    def __init__(self, wl, code, y_d, L, T, want_moves):
+        F = y_d.shape[0]
+        self.wl, self.code, self.y_d, self.L = wl, code, y_d, L
+        self.q = torch.empty(y_d.shape, dtype=torch.int8, device=DEV)
+        self.s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=DEV),
+                   "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)}
+        self.st = D.Stage2([(code, F)], L, T, "i8", DEV, want_moves=want_moves)
+
+    def stage1(self, raw=None):
+        wl = self.wl
+        D.stage1_quantized(self.code, self.L, self.y_d, float(wl.llr_scale), wl.crc_len, wl.crc_poly,
+                           q=self.q, out=self.s1, raw_stream=raw)
+
+    def record(self, tiles):
+        def rec(raw):
+            self.stage1(raw)
+            self.st.run([self.q], [self.s1["anchors"]], [self.s1["crc_ok"]], variant=tiles[0],
+                        blocks_per_cu=tiles[1], raw_stream=raw)
+        return rec
+
+    def result(self):
+        out = {k: v.cpu().numpy() for k, v in self.st.outs[0].items()}
+        out["crc_ok"] = self.s1["crc_ok"].cpu().numpy()
+        out["anchors"] = self.s1["anchors"].cpu().numpy()
+        out["q"] = self.q.cpu().numpy()
+        return out
+
+
+def run_pipeline(wl, F, L, T, seed, want_moves=True, tiles=None, in_flight=1, replays=2):
     """The step bench.py times: quantizer + stage 1 (one launch) and stage 2
     recorded as one HIP graph with autotuned per-iteration tiles (or the given
-    ones), replayed twice.  bench.py itself runs it with want_moves=False (no
-    move logs)."""
+    ones).  With in_flight = B, B such graphs with their own buffers are
+    replayed round-robin on B streams (replays per batch), so B batches run at
+    once; bench.py times the step that way, with want_moves=False (no move
+    logs).  Returns the outputs of every batch."""
     pay, c, y = synth.generate(wl, seed, 0, F)
     code = D.Code(wl.r, wl.m, DEV)
     y_d = torch.from_numpy(y).to(DEV)
-    q = torch.empty(y.shape, dtype=torch.int8, device=DEV)
-    s1 = {"anchors": torch.empty((F, L, code.N // 8), dtype=torch.uint8, device=DEV),
-          "crc_ok": torch.empty(F, dtype=torch.uint8, device=DEV)}
-    st = D.Stage2([(code, F)], L, T, "i8", DEV, want_moves=want_moves)
-    scale = float(wl.llr_scale)
-    D.stage1_quantized(code, L, y_d, scale, wl.crc_len, wl.crc_poly, q=q, out=s1)
+    batches = [Batch(wl, code, y_d, L, T, want_moves) for _ in range(in_flight)]
+    b0 = batches[0]
+    b0.stage1()
     torch.cuda.synchronize()
     if tiles is None:
-        variant, bpc = autotune.tune(st, [q], [s1["anchors"]], [s1["crc_ok"]], reps=1, use_cache=False)
-    else:
-        variant, bpc = tiles
-
-    def record(raw):
-        D.stage1_quantized(code, L, y_d, scale, wl.crc_len, wl.crc_poly, q=q, out=s1, raw_stream=raw)
-        st.run([q], [s1["anchors"]], [s1["crc_ok"]], variant=variant, blocks_per_cu=bpc, raw_stream=raw)
-
-    g = D.Graph(record)
-    g.launch()
-    g.launch()
+        tiles = autotune.tune(b0.st, [b0.q], [b0.s1["anchors"]], [b0.s1["crc_ok"]], reps=1, use_cache=False)
+    graphs = [D.Graph(b.record(tiles)) for b in batches]
+    streams = [torch.cuda.Stream() for _ in batches]
     torch.cuda.synchronize()
-    out = {k: v.cpu().numpy() for k, v in st.outs[0].items()}
-    out["crc_ok"] = s1["crc_ok"].cpu().numpy()
-    out["anchors"] = s1["anchors"].cpu().numpy()
-    out["q"] = q.cpu().numpy()
-    stats = st.stats.cpu().numpy()
-    del g
-    return c, y, out, stats, (variant, bpc)
+    for k in range(replays * in_flight):
+        graphs[k % in_flight].launch(streams[k % in_flight])
+    torch.cuda.synchronize()
+    outs = [b.result() for b in batches]
+    stats = [b.st.stats.cpu().numpy() for b in batches]
+    del graphs
+    if in_flight == 1:
+        return c, y, outs[0], stats[0], tuple(tiles)
+    return c, y, outs, stats, tuple(tiles)
 
 
 def check_sample(wl, L, T, out, rows):
@@ -122,3 +147,23 @@ def test_rm38_config_size():
     for k in ("cw", "k", "metric", "crc_ok", "anchors", "q"):
         assert np.array_equal(out2[k], out[k]), k
     assert np.array_equal(stats2, stats)
+
+
+def test_rm37_batches_in_flight():
+    """bench.py's timed loop: three batches in flight, each step's graph on its
+    own stream, replayed round-robin.  Every batch must hold exactly the
+    outputs of one batch decoded alone (and of the oracle on a sample)."""
+    wl = synth.RM37
+    F, L, T = 65536, 8, 8
+    say("case: RM(3,7) 65536 frames, one batch, bench configuration")
+    c, y, ref, stats, tiles = run_pipeline(wl, F, L, T, 0, want_moves=False)
+    say("case: RM(3,7) 65536 frames, 3 batches in flight, 3 replays each")
+    c3, y3, outs, stats3, _ = run_pipeline(wl, F, L, T, 0, want_moves=False, tiles=tiles, in_flight=3, replays=3)
+    for b, (out, sb) in enumerate(zip(outs, stats3)):
+        for k in ("cw", "k", "metric", "crc_ok", "anchors", "q"):
+            assert np.array_equal(out[k], ref[k]), (b, k)
+        assert np.array_equal(sb, stats), b
+    fail = np.nonzero(ref["crc_ok"] == 0)[0]
+    rng = np.random.default_rng(2)
+    rows = np.sort(np.concatenate([rng.choice(fail, 48, replace=False), [0, F - 1]]))
+    check_sample(wl, L, T, outs[-1], rows)
