@@ -24,6 +24,20 @@
 //   4. every lane keeps its L best (metric, number) keys in LDS; L rounds of
 //      a wave-wide minimum merge them, and lanes 0..L-1 rebuild and store the
 //      winners.
+//
+// Integer metric, order k <= 2 and K <= 32 (the OSD(2) of RM(2,7)): step 3
+// is a Gram matrix on the matrix cores instead.  With z_j = q_j (1 - 2 c0_j),
+// M(c0 xor x) = M(c0) + sum_j x_j z_j for any x, so with T = G diag(z) G^T
+// over the K basis rows g_a:
+//     M(c0 xor g_a)         = M(c0) + T_aa,
+//     M(c0 xor g_a xor g_b) = M(c0) + T_aa + T_bb - 2 T_ab,
+// exact in integers.  T is a K x N x K int8 product (|z_j| <= 127, rows 0/1)
+// with int32 sums: 16 x 16 tiles of v_mfma_i32_16x16x64_i8, three tiles
+// (two row blocks, the upper triangle) times N / 64 position chunks for
+// RM(2,7).  Every candidate then sits in one accumulator slot of one lane
+// (pairs a < b above the diagonal, singles on it, c0 in one slot below
+// it); L rounds of a wave minimum over 32-bit (metric, number) keys pick
+// the anchors.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -105,6 +119,36 @@ __device__ inline uint64_t wave_xor_u64(uint64_t v)
     v ^= dpp_partner<DPP_HALF_MIRROR>(v);
     v ^= dpp_partner<DPP_MIRROR>(v);
     return readlane_u64(v, 0) ^ readlane_u64(v, 16) ^ readlane_u64(v, 32) ^ readlane_u64(v, 48);
+}
+
+// Minimum over the wave of a 32-bit value (every lane returns it).
+__device__ inline uint32_t wave_min_u32(uint32_t v)
+{
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_1032, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_QUAD_2301, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_HALF_MIRROR, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, DPP_MIRROR, 0xF, 0xF, false));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// Sum over the wave (every lane returns it).
+__device__ inline int wave_sum_i32(int v)
+{
+    v += __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_1032, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(v, v, DPP_QUAD_2301, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(v, v, DPP_HALF_MIRROR, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(v, v, DPP_MIRROR, 0xF, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) + __builtin_amdgcn_readlane(v, 32) +
+           __builtin_amdgcn_readlane(v, 48);
+}
+
+// Bytes 0 / 1 of the four bits of nibble t of x: byte i is bit 4 t + i (the
+// shifted copies of the nibble in the 24-bit product do not overlap).
+__device__ inline uint32_t nibble_bytes(uint32_t x, int t)
+{
+    return __umul24((x >> (4 * t)) & 0xFu, 0x00204081u) & 0x01010101u;
 }
 
 // Ascending bitonic sort of the 64 E keys of a wave, E per lane (element
@@ -208,12 +252,148 @@ __device__ inline void build_candidate(uint64_t (&c)[W], const uint64_t (&c0)[W]
     }
 }
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ inline int pick4(const v4i& x, int j)
+{
+    return j == 0 ? x[0] : j == 1 ? x[1] : j == 2 ? x[2] : x[3];
+}
+
+// Candidate key of the Gram form: (metric - M(c0) + 2^15) << 10 | number.
+// |metric - M(c0)| <= 127 N <= 32512 and numbers < 2^10 (K <= 32, order
+// <= 2), so the keys order as (metric, number) and fit 26 bits.
+__device__ inline uint32_t gram_key(int delta, int num) { return ((uint32_t)(delta + 32768) << 10) | (uint32_t)num; }
+
+// Steps 3-4 of the Gram form (integer metric, order <= 2, K <= 16 GB):
+// T = G diag(z) G^T on the matrix cores, one key per candidate in the
+// accumulator slots, L rounds of a wave minimum, winners rebuilt by lanes
+// 0 .. L-1.  Lane (li, lg) supplies row (and column) 16 X + li of block X
+// at its 16 positions 64 w + 16 lg + e of chunk w: the A operand carries
+// z_j g_a(j), the B operand g_b(j) (0 / 1), so both use the same position
+// for a given byte and the sums do not depend on how the matrix core maps
+// bytes to the reduction index.  Slot j of the (R, C) tile holds
+// T[16 R + 4 lg + j][16 C + li].
+template <int W, int GB>
+__device__ __forceinline__ void gram_anchors(int lane, int64_t f, int N, int K, int order, int L,
+                                             const int8_t* qs, const int8_t* nqs, const uint64_t* rows,
+                                             const uint64_t (&c0)[W], int32_t* dT, uint64_t* win,
+                                             uint8_t* __restrict__ anchors, int32_t* __restrict__ metric_out)
+{
+    const int li = lane & 15, lg = lane >> 4;
+    const uint32_t* q4 = reinterpret_cast<const uint32_t*>(qs);
+    const uint32_t* nq4 = reinterpret_cast<const uint32_t*>(nqs);
+    v4i za[GB][W], gb[GB][W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        // z = q where c0 is 0, -q where it is 1 (byte select: v_perm picks
+        // byte i of q, or byte i of -q when c0's byte is 1)
+        const uint32_t cb = (uint32_t)(c0[w] >> (16 * lg)) & 0xFFFFu;
+        uint32_t zw[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t ct = nibble_bytes(cb, t);
+            const int qi = 16 * w + 4 * lg + t;
+            zw[t] = __builtin_amdgcn_perm(nq4[qi], q4[qi], 0x03020100u + (ct << 2));
+        }
+#pragma unroll
+        for (int X = 0; X < GB; ++X) {
+            const int a = 16 * X + li;
+            const uint64_t rw = a < K ? rows[a * W + w] : 0ull;
+            const uint32_t bits = (uint32_t)(rw >> (16 * lg)) & 0xFFFFu;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t e = nibble_bytes(bits, t);
+                gb[X][w][t] = (int)e;
+                za[X][w][t] = (int)(zw[t] & ((e << 8) - e));  // bytes 0xFF where e is 1
+            }
+        }
+    }
+    // tiles (0, 0), (0, 1), (1, 1)
+    constexpr int NT = GB == 2 ? 3 : 1;
+    v4i tt[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) tt[i] = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        tt[0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(za[0][w], gb[0][w], tt[0], 0, 0, 0);
+        if constexpr (GB == 2) {
+            tt[1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(za[0][w], gb[1][w], tt[1], 0, 0, 0);
+            tt[2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(za[1][w], gb[1][w], tt[2], 0, 0, 0);
+        }
+    }
+    // the diagonal, for every lane
+    {
+        const int j = li - 4 * lg;
+        if (j >= 0 && j < 4) {
+            dT[li] = pick4(tt[0], j);
+            if constexpr (GB == 2) dT[16 + li] = pick4(tt[NT - 1], j);
+        }
+    }
+    int M0 = 0;  // M(c0), for the metrics returned
+    if (metric_out) {
+        int part = 0;
+#pragma unroll
+        for (int h = 0; h < W; ++h)
+            if (64 * h + lane < N && ((c0[h] >> lane) & 1ull)) part += qs[64 * h + lane];
+        M0 = wave_sum_i32(part);
+    }
+    __syncthreads();
+    uint32_t key[NT][4];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int R = i == 2 ? 1 : 0, C = i == 0 ? 0 : 1;
+        const v4i da = *reinterpret_cast<const v4i*>(dT + 16 * R + 4 * lg);
+        const int b = 16 * C + li, db = dT[b];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int a = 16 * R + 4 * lg + j;
+            const int tv = tt[i][j];
+            uint32_t k = 0xFFFFFFFFu;
+            if (a == b) {
+                if (order >= 1 && a < K) k = gram_key(tv, 1 + a);                    // {a}
+            } else if (a < b) {
+                if (order >= 2 && b < K)                                              // {a, b}
+                    k = gram_key(da[j] + db - 2 * tv, 1 + K + a * (2 * K - a - 1) / 2 + b - a - 1);
+            } else if (i == 0 && a == 1 && b == 0) {
+                k = gram_key(0, 0);                                                   // c0
+            }
+            key[i][j] = k;
+        }
+    }
+    // L rounds: the smallest key above the last winner (keys are distinct;
+    // subtracting last + 1 sends the taken ones and the empty slots past 2^31)
+    uint32_t last = 0xFFFFFFFFu;
+    for (int t = 0; t < L; ++t) {
+        const uint32_t off = last + 1u;
+        uint32_t mn = 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < NT; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mn = min(mn, key[i][j] - off);
+        last = wave_min_u32(mn) + off;
+        if (lane == 0) win[t] = last;
+    }
+    __syncthreads();
+    if (lane < L) {
+        const uint32_t k = (uint32_t)win[lane];
+        const Pattern p = unrank(k & 0x3FFu, K);
+        uint64_t c[W];
+        build_candidate<W>(c, c0, rows, p);
+        uint8_t* dst = anchors + ((size_t)f * L + lane) * (N / 8);
+        for (int b = 0; b < N / 8; ++b) dst[b] = (uint8_t)(c[b >> 3] >> (8 * (b & 7)));
+        if (metric_out) metric_out[f * L + lane] = M0 + ((int)(k >> 10) - 32768);
+    }
+}
+
 // W: 64-bit words per codeword (N = 32 uses the low half of one word).
-template <int W, bool FLOAT>
+// GB: 0 = enumerate the candidates; 1 or 2 = integer metric of order <= 2
+// from the Gram matrix over GB blocks of 16 basis rows (K <= 16 GB).
+template <int W, bool FLOAT, int GB>
 __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr, int64_t F, int m, int r, int K,
                                                    int order, int L, uint8_t* __restrict__ anchors,
                                                    int32_t* __restrict__ metric_out)
 {
+    static_assert(GB == 0 || !FLOAT, "the Gram form is exact in integers only");
     const int N = 1 << m;
     const int NB = N / 8;
     const int lane = threadIdx.x;
@@ -221,7 +401,9 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
     if (f >= F) return;  // whole workgroup: no barrier is skipped by part of it
 
     __shared__ float ys[FLOAT ? MAXN : 1];
-    __shared__ int8_t qs[MAXN];
+    __shared__ __attribute__((aligned(16))) int8_t qs[MAXN];
+    __shared__ __attribute__((aligned(16))) int8_t nqs[GB ? MAXN : 1];  // -q (Gram form)
+    __shared__ __attribute__((aligned(16))) int32_t dT[GB ? 32 : 1];    // diagonal of T (Gram form)
     __shared__ uint64_t keys[FLOAT ? MAXN : 1];  // reliability keys (binary32 form)
     __shared__ uint16_t sorted[MAXN];
     __shared__ uint16_t info[MAXK];
@@ -242,6 +424,7 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
         } else {
             const int v = mpwsd::read_q1(((const int8_t*)llr)[f * N + j]);
             qs[j] = (int8_t)v;
+            if (GB) nqs[j] = (int8_t)-v;
             mag = (uint32_t)(v < 0 ? -(int)v : (int)v);
         }
         if (FLOAT) keys[j] = ((uint64_t)(0xFFFFFFFFu - mag) << 32) | (uint32_t)j;
@@ -341,6 +524,11 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
 #pragma unroll
     for (int w = 0; w < W; ++w) c0[w] = c0s[w];
 
+    if constexpr (GB > 0) {
+        gram_anchors<W, GB>(lane, f, N, K, order, L, qs, nqs, rows, c0, dT, win, anchors, metric_out);
+        return;
+    }
+
     // bit planes of q (integer metric)
     uint64_t plane[FLOAT ? 1 : W][8];
     if (!FLOAT) {
@@ -432,12 +620,19 @@ void launch_w(bool fl, const void* llr, int64_t F, int m, int r, int K, int orde
               int32_t* metric, hipStream_t s)
 {
     const size_t lds = (size_t)L * WAVE * sizeof(uint64_t);
+    const dim3 grid((unsigned)F);
     if (fl)
-        hipLaunchKernelGGL((osd_kernel<W, true>), dim3((unsigned)F), dim3(WAVE), lds, s, llr, F, m, r, K, order, L,
-                           anchors, metric);
+        hipLaunchKernelGGL((osd_kernel<W, true, 0>), grid, dim3(WAVE), lds, s, llr, F, m, r, K, order, L, anchors,
+                           metric);
+    else if (order <= 2 && K <= 16)
+        hipLaunchKernelGGL((osd_kernel<W, false, 1>), grid, dim3(WAVE), 0, s, llr, F, m, r, K, order, L, anchors,
+                           metric);
+    else if (order <= 2 && K <= 32)
+        hipLaunchKernelGGL((osd_kernel<W, false, 2>), grid, dim3(WAVE), 0, s, llr, F, m, r, K, order, L, anchors,
+                           metric);
     else
-        hipLaunchKernelGGL((osd_kernel<W, false>), dim3((unsigned)F), dim3(WAVE), lds, s, llr, F, m, r, K, order,
-                           L, anchors, metric);
+        hipLaunchKernelGGL((osd_kernel<W, false, 0>), grid, dim3(WAVE), lds, s, llr, F, m, r, K, order, L, anchors,
+                           metric);
 }
 
 }  // namespace

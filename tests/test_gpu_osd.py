@@ -50,6 +50,16 @@ ANCHOR_CASES = [
     ("rm37_K64_k1_L8", 3, 7, 1, 8, 2.0, 64),
     ("rm28_N256_k2_L4", 2, 8, 2, 4, 2.0, 48),
     ("rm27_k0_L1", 2, 7, 0, 1, 2.0, 64),
+    # integer form of order <= 2 with K <= 32 runs the Gram-matrix kernel:
+    # one block of 16 basis rows (K = 6, 16), two (K = 22, 26, 29), N = 32
+    # (half of each 64-position chunk empty) and N = 256 (four chunks)
+    ("rm15_N32_K6_k2_L16", 1, 5, 2, 16, 1.0, 64),
+    ("rm25_N32_K16_k2_L8", 2, 5, 2, 8, 1.5, 64),
+    ("rm35_N32_K26_k2_L8", 3, 5, 2, 8, 2.0, 64),
+    ("rm26_K22_k2_L32", 2, 6, 2, 32, 2.0, 64),
+    ("rm18_N256_K9_k2_L8", 1, 8, 2, 8, 0.0, 48),
+    ("rm27_k1_L8", 2, 7, 1, 8, 2.0, 64),
+    ("rm27_k2_L32", 2, 7, 2, 32, 1.5, 64),
 ]
 
 
@@ -129,3 +139,54 @@ def test_osd_always_on_decode_parity(name, r, m, order, L, T, ebn0, F, dtype):
     fer = float((ref["c"] != c).any(1).mean())
     say("  FER OSD alone %.3f, with MP-WSD %.3f" % (fer_anchor, fer))
     assert fer <= fer_anchor
+
+
+def test_osd_bench_size():
+    """bench.py --workload rm27osd: 65536 RM(2,7) frames at 2.5 dB, int8,
+    OSD(2) with L = 8 (the Gram-matrix kernel), always-on stage 2 with T = 4,
+    recorded as one HIP graph with autotuned tiles and no move logs; sampled
+    frames against the oracle, and every frame's metrics against its own
+    anchors (the search never returns a worse word than the best anchor)."""
+    from paper_2602_08501_amd import autotune
+    say("case: OSD(2) + stage 2, RM(2,7) 65536 frames, bench configuration")
+    wl = synth.Workload(r=2, m=7, k_pay=29, crc_len=0, ebn0_db=2.5, wid=4)
+    F, L, T, order = 65536, 8, 4, 2
+    pay, c, y = synth.generate(wl, 0, 0, F)
+    cd = code(2, 7)
+    y_d = torch.from_numpy(y).to(DEV)
+    q = torch.empty(y.shape, dtype=torch.int8, device=DEV)
+    s1 = {"anchors": torch.empty((F, L, 16), dtype=torch.uint8, device=DEV),
+          "metric": torch.empty((F, L), dtype=torch.int32, device=DEV)}
+    st = D.Stage2([(cd, F)], L, T, "i8", DEV, want_moves=False)
+    D.quantize(y_d, float(wl.llr_scale), out=q)
+    D.stage1_osd(cd, order, L, q, out=s1)
+    torch.cuda.synchronize()
+    tiles = autotune.tune(st, [q], [s1["anchors"]], [None], reps=1, use_cache=False)
+
+    def record(raw):
+        D.quantize(y_d, float(wl.llr_scale), out=q, raw_stream=raw)
+        D.stage1_osd(cd, order, L, q, out=s1, raw_stream=raw)
+        st.run([q], [s1["anchors"]], [None], variant=tiles[0], blocks_per_cu=tiles[1], raw_stream=raw)
+
+    g = D.Graph(record)
+    g.launch()
+    g.launch()
+    torch.cuda.synchronize()
+    del g
+    qn = q.cpu().numpy()
+    anc = unpack(s1["anchors"])
+    am = s1["metric"].cpu().numpy()
+    o = {k: v.cpu().numpy() for k, v in st.outs[0].items()}
+    assert np.array_equal(st.stats.cpu().numpy()[:2], [F, F * L])
+    # anchors sorted by (metric, candidate number): metrics ascending per frame
+    assert (np.diff(am, axis=1) >= 0).all()
+    # the decoded word's metric never exceeds the best anchor's
+    assert (o["metric"] <= am[:, 0]).all()
+    rng = np.random.default_rng(3)
+    rows = np.sort(np.concatenate([rng.choice(F, 62, replace=False), [0, F - 1]]))
+    ref = oracle.decode_osd_batch(2, 7, order, L, T, oracle.INT, qn[rows].astype(np.float64), threads=8)
+    assert np.array_equal(anc[rows], ref["anchors"])
+    assert np.array_equal(am[rows], ref["anchor_metric"].astype(np.int32))
+    assert np.array_equal(unpack(st.outs[0]["cw"])[rows], ref["c"])
+    assert np.array_equal(o["k"][rows], ref["k"])
+    assert np.array_equal(o["metric"][rows], ref["metric"].astype(np.int32))
