@@ -24,6 +24,7 @@
 #include <climits>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <thread>
 #include <vector>
 
@@ -298,11 +299,94 @@ double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-struct Pending {
-    uint64_t tag;
-    float scale;
-    double t_submit;
-    std::vector<float> y;
+// Submitted frames not yet admitted, first in first out: blocks of B rows of
+// N values, recycled through a short spare list, so that a growing backlog
+// neither allocates per frame nor copies what is queued.
+struct Waiting {
+    static constexpr size_t B = 4096;  // rows per block
+    static constexpr size_t kSpare = 16;
+    struct Block {
+        std::unique_ptr<float[]> y;  // [B][N]
+        float scale[B];
+        uint64_t tag[B];
+        double t[B];
+    };
+    Waiting() = default;
+    Waiting(const Waiting&) = delete;  // move-only (so is the code state that holds it)
+    Waiting& operator=(const Waiting&) = delete;
+    Waiting(Waiting&&) = default;
+    Waiting& operator=(Waiting&&) = default;
+    int N = 0;
+    std::deque<std::unique_ptr<Block>> blocks;  // front: the oldest rows
+    std::vector<std::unique_ptr<Block>> spare;
+    size_t head = 0;   // first queued row in the front block
+    size_t count = 0;  // queued rows
+    size_t size() const { return count; }
+    bool empty() const { return count == 0; }
+    void push(const float* row, float sc, uint64_t tg, double ts)
+    {
+        const size_t pos = head + count;
+        if (pos / B == blocks.size()) blocks.push_back(take());
+        Block& b = *blocks[pos / B];
+        const size_t k = pos % B;
+        std::memcpy(&b.y[k * N], row, sizeof(float) * N);
+        b.scale[k] = sc;
+        b.tag[k] = tg;
+        b.t[k] = ts;
+        ++count;
+    }
+    // Row k from the front (k < count): its block, and *i its index there.
+    const Block& row(size_t k, size_t* i) const
+    {
+        const size_t pos = head + k;
+        *i = pos % B;
+        return *blocks[pos / B];
+    }
+    // Copies the first n rows into dst (contiguous).
+    void copy_front(size_t n, float* dst) const
+    {
+        size_t pos = head, done = 0;
+        while (done < n) {
+            const size_t i = pos % B, m = std::min(n - done, B - i);
+            std::memcpy(dst + done * N, &blocks[pos / B]->y[i * N], sizeof(float) * N * m);
+            done += m;
+            pos += m;
+        }
+    }
+    void pop(size_t n)
+    {
+        head += n;
+        count -= n;
+        while (head >= B) {
+            give(std::move(blocks.front()));
+            blocks.pop_front();
+            head -= B;
+        }
+        if (count == 0) {
+            while (!blocks.empty()) {
+                give(std::move(blocks.front()));
+                blocks.pop_front();
+            }
+            head = 0;
+        }
+    }
+
+private:
+    std::unique_ptr<Block> take()
+    {
+        if (!spare.empty()) {
+            std::unique_ptr<Block> b = std::move(spare.back());
+            spare.pop_back();
+            return b;
+        }
+        std::unique_ptr<Block> b(new Block);
+        b->y.reset(new float[B * (size_t)N]);
+        return b;
+    }
+    void give(std::unique_ptr<Block> b)
+    {
+        if (spare.size() < kSpare) spare.push_back(std::move(b));
+    }
 };
 
 struct Code {
@@ -313,7 +397,7 @@ struct Code {
     std::vector<int> free_slots;
     std::vector<uint64_t> slot_tag;
     std::vector<double> slot_t;
-    std::deque<Pending> waiting;
+    Waiting waiting;
     int in_slots = 0;  // admitted, not yet harvested
     int cur = 0;       // active list the next tick searches
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -411,17 +495,18 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
         Code& c = s->codes[ci];
         TickBuf::PerCode& p = tb.pc[ci];
         const int n_new = (int)std::min(c.waiting.size(), c.free_slots.size());
+        c.waiting.copy_front((size_t)n_new, p.y);
         for (int i = 0; i < n_new; ++i) {
-            Pending& w = c.waiting.front();
+            size_t w;
+            const Waiting::Block& b = c.waiting.row((size_t)i, &w);
             const int slot = c.free_slots.back();
             c.free_slots.pop_back();
-            std::memcpy(p.y + (size_t)i * c.N, w.y.data(), sizeof(float) * c.N);
-            p.scale[i] = w.scale;
+            p.scale[i] = b.scale[w];
             p.slot[i] = slot;
-            c.slot_tag[slot] = w.tag;
-            c.slot_t[slot] = w.t_submit;
-            c.waiting.pop_front();
+            c.slot_tag[slot] = b.tag[w];
+            c.slot_t[slot] = b.t[w];
         }
+        c.waiting.pop((size_t)n_new);
         c.in_slots += n_new;
         p.maxrec = c.in_slots;
         if (c.in_slots == 0) {
@@ -507,6 +592,7 @@ extern "C" int mpwsd_server_create(const mpwsd_server_code* codes, int ncodes, v
         Code c;
         c.c = codes[i];
         c.N = 1 << codes[i].m;
+        c.waiting.N = c.N;
         c.KP = c.N < 64 ? 64 : c.N;
         c.NB = c.N / 8;
         c.lay = layout(codes[i]);
@@ -557,14 +643,7 @@ extern "C" int mpwsd_server_submit(mpwsd_server* s, int code, int n, const float
         return fail(MPWSD_ERR_ARG, "mpwsd_server_submit: bad arguments");
     Code& c = s->codes[code];
     const double t = now_s();
-    for (int i = 0; i < n; ++i) {
-        Pending p;
-        p.tag = tags[i];
-        p.scale = scale[i];
-        p.t_submit = t;
-        p.y.assign(y + (size_t)i * c.N, y + (size_t)(i + 1) * c.N);
-        c.waiting.push_back(std::move(p));
-    }
+    for (int i = 0; i < n; ++i) c.waiting.push(y + (size_t)i * c.N, scale[i], tags[i], t);
     s->submitted += n;
     return MPWSD_OK;
 }
