@@ -20,11 +20,21 @@ __device__ inline uint32_t read_q4(uint32_t x)
 }
 __device__ inline int read_q1(int8_t v) { return v < -127 ? -127 : (int)v; }
 
+// Bytes 0 / 1 from the low 4 bits of nib: byte b is bit b (the four shifted
+// copies of the nibble in the 24-bit product do not overlap).
+__device__ inline uint32_t bit_bytes(uint32_t nib) { return __umul24(nib & 15u, 0x00204081u) & 0x01010101u; }
+
+// Sum of the int8 lanes of x whose bit is set in the low 4 bits of nib.
+__device__ inline int masked_sum4(uint32_t x, uint32_t nib, int acc)
+{
+    return __builtin_amdgcn_sdot4((int)x, (int)bit_bytes(nib), acc, false);
+}
+
 // Negate the int8 lanes of x whose bit is set in the low 4 bits of nib
 // (two's complement per byte, no carry between bytes).
 __device__ inline uint32_t neg_bytes(uint32_t x, uint32_t nib)
 {
-    const uint32_t one = ((nib & 15u) * 0x00204081u) & 0x01010101u;  // bit b -> byte b
+    const uint32_t one = bit_bytes(nib);  // bit b -> byte b
     const uint32_t t = x ^ (one * 0xFFu);
     return ((t & 0x7F7F7F7Fu) + one) ^ (t & 0x80808080u);
 }

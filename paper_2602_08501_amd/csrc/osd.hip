@@ -144,12 +144,8 @@ __device__ inline int wave_sum_i32(int v)
            __builtin_amdgcn_readlane(v, 48);
 }
 
-// Bytes 0 / 1 of the four bits of nibble t of x: byte i is bit 4 t + i (the
-// shifted copies of the nibble in the 24-bit product do not overlap).
-__device__ inline uint32_t nibble_bytes(uint32_t x, int t)
-{
-    return __umul24((x >> (4 * t)) & 0xFu, 0x00204081u) & 0x01010101u;
-}
+// Bytes 0 / 1 of the four bits of nibble t of x: byte i is bit 4 t + i.
+__device__ inline uint32_t nibble_bytes(uint32_t x, int t) { return mpwsd::bit_bytes(x >> (4 * t)); }
 
 // Ascending bitonic sort of the 64 E keys of a wave, E per lane (element
 // lane * E + h in x[h]): partners closer than E in registers, the others by

@@ -124,15 +124,9 @@ __global__ __launch_bounds__(256) void srv_enter_kernel(
                 v4i_t zv;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) {
-                    uint32_t wz = 0;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int v = (int8_t)((uint32_t)qv[d] >> (8 * b));
-                        const int bit = (bits >> (4 * d + b)) & 1;
-                        m += bit ? v : 0;
-                        wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
-                    }
-                    zv[d] = (int)wz;
+                    const uint32_t nib = bits >> (4 * d);
+                    m = mpwsd::masked_sum4((uint32_t)qv[d], nib, m);
+                    zv[d] = (int)mpwsd::neg_bytes((uint32_t)qv[d], ~nib);  // -z: q where the bit is 1, else -q
                 }
                 if (join) {
                     *(v4i_t*)(zneg + (size_t)col * KP + j0) = zv;

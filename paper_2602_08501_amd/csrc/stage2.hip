@@ -191,6 +191,7 @@ __global__ __launch_bounds__(256) void init_kernel(
     int32_t* __restrict__ out_metric, int32_t* __restrict__ out_moves, int32_t* __restrict__ stats)
 {
     const int PP = KP / 16;  // pieces per item (4, 8 or 16: an item's pieces share a wave)
+    const int pps = __builtin_ctz((unsigned)PP);
     const int NB = N / 8;
     const int64_t nfail = hdr[0];
     const int64_t part1 = F * PP;
@@ -203,12 +204,12 @@ __global__ __launch_bounds__(256) void init_kernel(
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ((total + 63) & ~int64_t(63));
          g += (int64_t)gridDim.x * blockDim.x) {
         if (g >= total) continue;  // whole items: total and part1 are multiples of PP
-        const int piece = (int)(g % PP);
+        const int piece = (int)g & (PP - 1);
         const int j0 = 16 * piece;
         const bool inpos = j0 < N;
         if (g < part1) {
             // ---- frame f
-            const int64_t f = g / PP;
+            const int64_t f = g >> pps;
             if (out_moves) {
                 if (log16) {
                     // 16-byte stores: a frame's pieces write consecutive quads
@@ -224,12 +225,8 @@ __global__ __launch_bounds__(256) void init_kernel(
             if (!FLOAT && inpos) {
                 const v4i qv = *(const v4i*)((const int8_t*)llr + (size_t)f * N + j0);
 #pragma unroll
-                for (int d = 0; d < 4; ++d) {
-                    const uint32_t wq = mpwsd::read_q4((uint32_t)qv[d]);
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        part += ((bits >> (4 * d + b)) & 1) ? (int)(int8_t)(wq >> (8 * b)) : 0;
-                }
+                for (int d = 0; d < 4; ++d)
+                    part = mpwsd::masked_sum4(mpwsd::read_q4((uint32_t)qv[d]), bits >> (4 * d), part);
             }
             for (int o = 1; o < PP; o <<= 1) part += __shfl_xor(part, o);
             if (inpos) *(uint16_t*)(out_cw + (size_t)f * NB + 2 * piece) = (uint16_t)bits;
@@ -252,10 +249,10 @@ __global__ __launch_bounds__(256) void init_kernel(
                 }
             }
         } else {
-            // ---- column c of the failing frames
-            const int64_t col = (g - part1) / PP;
-            const int64_t s = col / L;
-            const int k = (int)(col % L);
+            // ---- column c of the failing frames (c < F L <= 2^30: 32-bit division)
+            const uint32_t col = (uint32_t)((g - part1) >> pps);
+            const uint32_t s = col / (uint32_t)L;
+            const int k = (int)(col - s * (uint32_t)L);
             const int64_t f = fid[s];
             const uint32_t bits = inpos ? *(const uint16_t*)(anchors + ((size_t)f * L + k) * NB + 2 * piece) : 0u;
             int part = 0;
@@ -266,15 +263,9 @@ __global__ __launch_bounds__(256) void init_kernel(
 #pragma unroll
                     for (int d = 0; d < 4; ++d) {
                         const uint32_t wq = mpwsd::read_q4((uint32_t)qv[d]);
-                        uint32_t wz = 0;
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) {
-                            const int v = (int8_t)(wq >> (8 * b));
-                            const int bit = (bits >> (4 * d + b)) & 1;
-                            part += bit ? v : 0;
-                            wz |= (uint32_t)(uint8_t)(bit ? v : -v) << (8 * b);  // -z
-                        }
-                        zv[d] = (int)wz;
+                        const uint32_t nib = bits >> (4 * d);
+                        part = mpwsd::masked_sum4(wq, nib, part);
+                        zv[d] = (int)mpwsd::neg_bytes(wq, ~nib);  // -z: q where the bit is 1, -q where it is 0
                     }
                 }
                 *(v4i*)((int8_t*)zbuf + (size_t)col * KP + j0) = zv;
