@@ -100,13 +100,14 @@ def workload(args, synth):
     return segs, L, T, radius, osd
 
 
-def recorded_traffic(workload_name):
+def recorded_traffic(args):
     """HBM bytes per search launch from the committed counter summary, or None
-    when the kernel source changed since the counters were taken (or there is
-    no summary for this workload)."""
+    when the kernel source changed since the counters were taken, or there is
+    no summary for this workload (the counters were taken on the default
+    RM(3,7) batch: no other workload, frame count or Eb/N0)."""
     import hashlib
     import re
-    if workload_name != "rm37":
+    if args.workload != "rm37" or args.frames or args.ebn0 is not None:
         return None
     path = os.path.join(ROOT, "profiles", "search_pw_rm37_65536f_hbm_traffic.txt")
     try:
@@ -352,7 +353,7 @@ def main():
                    "fer_stage1_first_anchor": fer1},
         "stage2_move_evals_per_s": move_evals / (launches.sum() * 1e-3),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MI355X_INT8_DENSE_TOPS, "unit": "TOP/s",
-                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(args.workload),
+                     "frac": achieved / MI355X_INT8_DENSE_TOPS, "traffic": recorded_traffic(args),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 KiB)",
                      "kernel": ("search_i8_multi_kernel" if nseg > 1 else
                                 "search_pw_kernel" if codes[0].grouped is not None else "search_i8_kernel"),
