@@ -467,7 +467,10 @@ int mpwsd_server_create(const mpwsd_server_code* codes, int ncodes, void* arena,
                         mpwsd_server** server);
 
 /* Queues n frames of code `code`: y host [n][N] float, scale[n] quantizer
- * scales (8 / sigma^2), tags[n].  The data is copied; nothing is enqueued. */
+ * scales (8 / sigma^2), tags[n].  The data is copied; nothing is enqueued.
+ * Submission may run on other threads than the one that calls
+ * mpwsd_server_tick and mpwsd_server_poll (each call locks the code's
+ * queue); tick, poll and destroy stay on one thread. */
 int mpwsd_server_submit(mpwsd_server* server, int code, int n, const float* y, const float* scale,
                         const uint64_t* tags);
 
@@ -485,9 +488,11 @@ int mpwsd_server_destroy(mpwsd_server* server);
 /*
  * mpwsd_serve_trace - a real-time load generator around a server: frame i of
  * the trace (code[i], y row row[i] of that code's pool, scale[i]) is
- * submitted when arrival[i] seconds have passed since the start, the server
- * is ticked continuously, and the result of frame i is written to out[i]
- * (tag = i).  pools[c] is a host [rows][N] float array for code c.
+ * submitted when arrival[i] seconds have passed since the start (by a
+ * producer thread of its own), the calling thread ticks the server
+ * continuously, and the result of frame i is written to out[i] (tag = i),
+ * its t_submit being the scheduled arrival (so latencies include any delay
+ * in submitting).  pools[c] is a host [rows][N] float array for code c.
  * Returns 0 when every frame completed.
  */
 int mpwsd_serve_trace(mpwsd_server* server, int64_t n, const int32_t* code, const int64_t* row,

@@ -20,11 +20,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -329,23 +331,15 @@ struct Waiting {
         b.t[k] = ts;
         ++count;
     }
-    // Row k from the front (k < count): its block, and *i its index there.
-    const Block& row(size_t k, size_t* i) const
+    // The blocks that hold the first n rows, and the first row's index in
+    // the first of them.  Pushes only append (rows past the last queued one,
+    // new blocks at the back), so these rows and blocks stay as they are
+    // until pop: a reader may use them without the lock.
+    size_t front_blocks(size_t n, std::vector<const Block*>* out) const
     {
-        const size_t pos = head + k;
-        *i = pos % B;
-        return *blocks[pos / B];
-    }
-    // Copies the first n rows into dst (contiguous).
-    void copy_front(size_t n, float* dst) const
-    {
-        size_t pos = head, done = 0;
-        while (done < n) {
-            const size_t i = pos % B, m = std::min(n - done, B - i);
-            std::memcpy(dst + done * N, &blocks[pos / B]->y[i * N], sizeof(float) * N * m);
-            done += m;
-            pos += m;
-        }
+        out->clear();
+        for (size_t b = 0; n > 0 && b <= (head + n - 1) / B; ++b) out->push_back(blocks[b].get());
+        return head;
     }
     void pop(size_t n)
     {
@@ -391,7 +385,11 @@ struct Code {
     std::vector<int> free_slots;
     std::vector<uint64_t> slot_tag;
     std::vector<double> slot_t;
+    // submissions may come from another thread than the ticks: the waiting
+    // queue is the only state they share, under this lock
+    std::unique_ptr<std::mutex> mu = std::make_unique<std::mutex>();
     Waiting waiting;
+    std::vector<const Waiting::Block*> front;  // the ticking thread's view of the queue's front
     int in_slots = 0;  // admitted, not yet harvested
     int cur = 0;       // active list the next tick searches
     template <typename T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -419,7 +417,8 @@ struct mpwsd_server {
     TickBuf ticks[2];
     int next_tick = 0;
     std::deque<mpwsd_result> done;
-    int64_t submitted = 0, returned = 0;
+    std::atomic<int64_t> submitted{0};
+    int64_t returned = 0;
 };
 
 namespace {
@@ -488,19 +487,30 @@ int enqueue_tick(mpwsd_server* s, TickBuf& tb)
     for (size_t ci = 0; ci < s->codes.size(); ++ci) {
         Code& c = s->codes[ci];
         TickBuf::PerCode& p = tb.pc[ci];
-        const int n_new = (int)std::min(c.waiting.size(), c.free_slots.size());
-        c.waiting.copy_front((size_t)n_new, p.y);
+        // the lock covers reading the queue's front, not the copies: a
+        // submitting thread only appends meanwhile
+        int n_new;
+        size_t h;
+        {
+            std::lock_guard<std::mutex> lock(*c.mu);
+            n_new = (int)std::min(c.waiting.size(), c.free_slots.size());
+            h = c.waiting.front_blocks((size_t)n_new, &c.front);
+        }
         for (int i = 0; i < n_new; ++i) {
-            size_t w;
-            const Waiting::Block& b = c.waiting.row((size_t)i, &w);
+            const size_t pos = h + (size_t)i, w = pos % Waiting::B;
+            const Waiting::Block& b = *c.front[pos / Waiting::B];
             const int slot = c.free_slots.back();
             c.free_slots.pop_back();
+            std::memcpy(p.y + (size_t)i * c.N, &b.y[w * c.N], sizeof(float) * c.N);
             p.scale[i] = b.scale[w];
             p.slot[i] = slot;
             c.slot_tag[slot] = b.tag[w];
             c.slot_t[slot] = b.t[w];
         }
-        c.waiting.pop((size_t)n_new);
+        if (n_new > 0) {
+            std::lock_guard<std::mutex> lock(*c.mu);
+            c.waiting.pop((size_t)n_new);
+        }
         c.in_slots += n_new;
         p.maxrec = c.in_slots;
         if (c.in_slots == 0) {
@@ -637,7 +647,10 @@ extern "C" int mpwsd_server_submit(mpwsd_server* s, int code, int n, const float
         return fail(MPWSD_ERR_ARG, "mpwsd_server_submit: bad arguments");
     Code& c = s->codes[code];
     const double t = now_s();
-    for (int i = 0; i < n; ++i) c.waiting.push(y + (size_t)i * c.N, scale[i], tags[i], t);
+    {
+        std::lock_guard<std::mutex> lock(*c.mu);
+        for (int i = 0; i < n; ++i) c.waiting.push(y + (size_t)i * c.N, scale[i], tags[i], t);
+    }
     s->submitted += n;
     return MPWSD_OK;
 }
@@ -652,7 +665,17 @@ extern "C" int mpwsd_server_tick(mpwsd_server* s, int64_t* in_flight)
         if (tb.busy && hipEventQuery(tb.ev) == hipSuccess) harvest(s, tb);
     }
     bool work = false;
-    for (auto& c : s->codes) work = work || c.in_slots > 0 || !c.waiting.empty();
+    for (auto& c : s->codes) {
+        if (c.in_slots > 0) {
+            work = true;
+            break;
+        }
+        std::lock_guard<std::mutex> lock(*c.mu);
+        if (!c.waiting.empty()) {
+            work = true;
+            break;
+        }
+    }
     if (work) {
         TickBuf& tb = s->ticks[s->next_tick];
         if (tb.busy) {  // both in flight: wait for the older one
@@ -712,20 +735,41 @@ extern "C" int mpwsd_serve_trace(mpwsd_server* s, int64_t n, const int32_t* code
         if (code[i] < 0 || code[i] >= (int)s->codes.size() || !pools[code[i]] || row[i] < 0)
             return fail(MPWSD_ERR_ARG, "mpwsd_serve_trace: bad trace entry %lld", (long long)i);
     const double t0 = now_s();
-    int64_t next = 0, got = 0;
+    // a producer thread submits each frame at its arrival time (as requests
+    // arriving on their own threads would); this thread ticks and polls
+    std::atomic<bool> stop{false};
+    std::thread producer([&]() {
+        const int nc = (int)s->codes.size();
+        int64_t i = 0;
+        while (i < n && !stop.load(std::memory_order_relaxed)) {
+            const double wait = arrival[i] - (now_s() - t0);
+            if (wait > 0.0) {
+                if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 1e-4));
+                continue;
+            }
+            // every frame that has arrived by now, one lock per code; each
+            // frame carries its scheduled arrival as its submission time
+            const double t = now_s() - t0;
+            int64_t j = i;
+            while (j < n && arrival[j] <= t) ++j;
+            for (int c = 0; c < nc; ++c) {
+                Code& cd = s->codes[c];
+                std::lock_guard<std::mutex> lock(*cd.mu);
+                for (int64_t f = i; f < j; ++f)
+                    if (code[f] == c) cd.waiting.push(pools[c] + (size_t)row[f] * cd.N, scale[f], (uint64_t)f,
+                                                      t0 + arrival[f]);
+            }
+            s->submitted += j - i;
+            i = j;
+        }
+    });
+    int rc = MPWSD_OK;
+    int64_t got = 0;
     std::vector<mpwsd_result> buf(4096);
     while (got < n) {
-        const double t = now_s() - t0;
-        while (next < n && arrival[next] <= t) {
-            const int c = code[next];
-            const uint64_t tag = (uint64_t)next;
-            const int rc = mpwsd_server_submit(s, c, 1, pools[c] + (size_t)row[next] * s->codes[c].N, &scale[next], &tag);
-            if (rc != MPWSD_OK) return rc;
-            ++next;
-        }
         int64_t inflight = 0;
-        int rc = mpwsd_server_tick(s, &inflight);
-        if (rc != MPWSD_OK) return rc;
+        rc = mpwsd_server_tick(s, &inflight);
+        if (rc != MPWSD_OK) break;
         int k;
         while ((k = mpwsd_server_poll(s, buf.data(), (int)buf.size())) > 0) {
             for (int i = 0; i < k; ++i) {
@@ -734,11 +778,9 @@ extern "C" int mpwsd_serve_trace(mpwsd_server* s, int64_t n, const int32_t* code
             }
             got += k;
         }
-        if (inflight == 0 && next < n) {
-            // idle until the next arrival
-            const double wait = arrival[next] - (now_s() - t0);
-            if (wait > 2e-4) std::this_thread::sleep_for(std::chrono::duration<double>(wait - 1e-4));
-        }
+        if (inflight == 0 && got < n) std::this_thread::sleep_for(std::chrono::microseconds(20));  // idle
     }
-    return MPWSD_OK;
+    stop.store(true);
+    producer.join();
+    return rc;
 }
