@@ -404,6 +404,7 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
     __shared__ uint16_t sorted[MAXN];
     __shared__ uint16_t info[MAXK];
     __shared__ uint16_t mrb[MAXK];
+    __shared__ uint8_t pivlane[MAXK];  // lane holding the row of pivot t
     __shared__ uint64_t rows[MAXK * W];
     __shared__ uint64_t c0s[W];
     __shared__ uint64_t win[32];
@@ -474,35 +475,51 @@ __global__ __launch_bounds__(WAVE) void osd_kernel(const void* __restrict__ llr,
         for (int w = 0; w < W; ++w)
             row[w] = (lane < K && (((uint32_t)w & ~(a >> 6)) == 0)) ? low : 0;
     }
-    bool pivoted = false;
-    int pivnum = 0;
-    int count = 0;
-    for (int s = 0; s < N && count < K; ++s) {
-        const int j = __builtin_amdgcn_readfirstlane((int)sorted[s]);
-        const int ws = j >> 6, bs = j & 63;
-        uint64_t rw = row[0];
+    // the reliability order in registers (rank 64 h + t in lane t of srt[h]),
+    // read with v_readlane; the pivot rows as a scalar lane mask
+    uint32_t srt[W];
 #pragma unroll
-        for (int w = 1; w < W; ++w)
-            if (ws == w) rw = row[w];
-        const bool bit = (rw >> bs) & 1ull;
-        const uint64_t cand = __ballot(bit && !pivoted);
-        if (cand == 0) continue;  // column j depends on the basis so far
-        const int p = __builtin_ctzll(cand);
+    for (int h = 0; h < W; ++h) srt[h] = 64 * h + lane < N ? sorted[64 * h + lane] : 0u;
+    uint64_t piv = 0;
+    int count = 0;
+#pragma unroll
+    for (int h = 0; h < W; ++h) {
+        const int nh = N - 64 * h < 64 ? N - 64 * h : 64;
+        for (int t = 0; t < nh && count < K; ++t) {
+            const int j = __builtin_amdgcn_readlane((int)srt[h], t);
+            const int ws = j >> 6, bs = j & 63;
+            uint64_t rw = row[0];
+#pragma unroll
+            for (int w = 1; w < W; ++w)
+                if (ws == w) rw = row[w];
+            const bool bit = (rw >> bs) & 1ull;
+            const uint64_t cand = __ballot(bit) & ~piv;
+            if (cand == 0) continue;  // column j depends on the basis so far
+            const int p = __builtin_ctzll(cand);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const uint64_t pr = readlane_u64(row[w], p);
+                if (bit && lane != p) row[w] ^= pr;
+            }
+            piv |= 1ull << p;
+            if (lane == 0) {
+                mrb[count] = (uint16_t)j;
+                pivlane[count] = (uint8_t)p;
+            }
+            ++count;
+        }
+    }
+    __syncthreads();
+    // pivot t's row (held by lane pivlane[t]) to rows[t]
+    {
+        const int src = lane < K ? (int)pivlane[lane] : lane;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            const uint64_t pr = readlane_u64(row[w], p);
-            if (bit && lane != p) row[w] ^= pr;
+            const uint64_t v = ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(row[w] >> 32), src) << 32) |
+                               (uint32_t)__shfl((int)(uint32_t)row[w], src);
+            if (lane < K) rows[lane * W + w] = v;
         }
-        if (lane == p) {
-            pivoted = true;
-            pivnum = count;
-        }
-        if (lane == 0) mrb[count] = (uint16_t)j;
-        ++count;
     }
-    if (pivoted)
-#pragma unroll
-        for (int w = 0; w < W; ++w) rows[pivnum * W + w] = row[w];
     __syncthreads();
 
     // c0: the codeword with the hard decisions on the basis
