@@ -1130,23 +1130,32 @@ __global__ __launch_bounds__(256) void resolve_f32_kernel(
 // 64 / LP frames per wave; the new centres stay in registers and are compared
 // word by word across the frame's lanes.  The frames with a column left to
 // search form the next frame list (all failing frames in iteration 0).
+// Kept columns and frames are gathered in LDS and appended to the next lists
+// with one global atomic per flush: a wave adds at most 64 of each per pass, a
+// workgroup 256.
+struct ResolveLds {
+    static constexpr int KBUF = 1024;
+    int32_t kcol[KBUF], kfrm[KBUF];
+    int kcnt[2];
+    unsigned long long kbase;
+};
+
+// The resolve of one segment by the workgroups bid = 0 .. nbid - 1 of a launch.
 template <bool FLOAT, int NW>
-__global__ __launch_bounds__(256) void resolve_merge_kernel(
-    void* __restrict__ zbuf, uint32_t* __restrict__ cw, int32_t* __restrict__ metric,
-    const uint8_t* __restrict__ moves, int KP, int64_t P, int32_t* __restrict__ hdr, int t, int T,
-    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int LP,
+__device__ __forceinline__ void resolve_merge_body(
+    ResolveLds& sh, int bid, int nbid, void* __restrict__ zbuf, uint32_t* __restrict__ cw,
+    int32_t* __restrict__ metric, const uint8_t* __restrict__ moves, int KP, int64_t P, int32_t* __restrict__ hdr,
+    int t, int T, unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int LP,
     int32_t* __restrict__ out_moves, int32_t* __restrict__ tag, const int32_t* __restrict__ fl_in,
     int32_t* __restrict__ fl_out, int32_t* __restrict__ act_out, int fcap)
 {
     constexpr int N = 32 * NW;
     typedef int v4i_t __attribute__((ext_vector_type(4)));
-    // kept columns and frames are gathered in LDS and appended to the next
-    // lists with one global atomic per flush: a wave adds at most 64 of each
-    // per pass, a workgroup 256
-    constexpr int KBUF = 1024;
-    __shared__ int32_t kcol[KBUF], kfrm[KBUF];
-    __shared__ int kcnt[2];
-    __shared__ unsigned long long kbase;
+    constexpr int KBUF = ResolveLds::KBUF;
+    int32_t* kcol = sh.kcol;
+    int32_t* kfrm = sh.kfrm;
+    int* kcnt = sh.kcnt;
+    unsigned long long& kbase = sh.kbase;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int per_wave = WAVE / LP;
     const int g = lane / LP, k = lane % LP, gbase = g * LP;
@@ -1156,7 +1165,7 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
     // the first pass's list entry is read before the list length is known
     // (the two loads are in flight together); an entry past the length is
     // stale and unused.  fcap is the list's capacity.
-    const int i0 = blockIdx.x * fpb + wave * per_wave + g;
+    const int i0 = bid * fpb + wave * per_wave + g;
     int s_first = fl_in && i0 < fcap ? fl_in[i0] : i0;
     const int nfr = fl_in ? hdr[ncol(t) + 1] : hdr[0];
     if (threadIdx.x == 0) kcnt[0] = kcnt[1] = 0;
@@ -1175,7 +1184,7 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
         if (threadIdx.x == 0) kcnt[0] = kcnt[1] = 0;
         __syncthreads();
     };
-    for (int b0 = blockIdx.x * fpb; b0 < nfr; b0 += gridDim.x * fpb) {  // the same passes for the whole workgroup
+    for (int b0 = bid * fpb; b0 < nfr; b0 += nbid * fpb) {  // the same passes for the whole workgroup
         const int i = b0 + wave * per_wave + g;
         const bool ok = i < nfr && k < L;
         const int s = !ok ? 0 : i == i0 ? s_first : fl_in ? fl_in[i] : i;
@@ -1289,6 +1298,61 @@ __global__ __launch_bounds__(256) void resolve_merge_kernel(
         }
     }
     if (merge) flush();
+}
+
+template <bool FLOAT, int NW>
+__global__ __launch_bounds__(256) void resolve_merge_kernel(
+    void* __restrict__ zbuf, uint32_t* __restrict__ cw, int32_t* __restrict__ metric,
+    const uint8_t* __restrict__ moves, int KP, int64_t P, int32_t* __restrict__ hdr, int t, int T,
+    unsigned long long* __restrict__ keys, const int32_t* __restrict__ fid, int L, int LP,
+    int32_t* __restrict__ out_moves, int32_t* __restrict__ tag, const int32_t* __restrict__ fl_in,
+    int32_t* __restrict__ fl_out, int32_t* __restrict__ act_out, int fcap)
+{
+    __shared__ ResolveLds sh;
+    resolve_merge_body<FLOAT, NW>(sh, blockIdx.x, gridDim.x, zbuf, cw, metric, moves, KP, P, hdr, t, T, keys, fid, L,
+                                  LP, out_moves, tag, fl_in, fl_out, act_out, fcap);
+}
+
+// One resolve launch for the segments of a multi-code call: segment i takes
+// the workgroups [b_end of segment i - 1, b_end of segment i).
+struct SegResolve {
+    void* z;
+    uint32_t* cw;
+    int32_t* metric;
+    const uint8_t* moves;
+    int64_t P;
+    int32_t* hdr;
+    unsigned long long* keys;
+    const int32_t* fid;
+    int32_t* out_moves;
+    int32_t* tag;
+    const int32_t* fl_in;
+    int32_t* fl_out;
+    int32_t* act_out;
+    int KP, NW, fcap, b_end;
+};
+struct MultiResolve {
+    SegResolve s[kMaxSeg];
+    int nseg;
+};
+
+template <bool FLOAT>
+__global__ __launch_bounds__(256) void resolve_merge_multi_kernel(MultiResolve mr, int t, int T, int L, int LP)
+{
+    __shared__ ResolveLds sh;
+    int i = 0;
+    while (i + 1 < mr.nseg && (int)blockIdx.x >= mr.s[i].b_end) ++i;
+    const SegResolve& g = mr.s[i];
+    const int b0 = i == 0 ? 0 : mr.s[i - 1].b_end;
+    const int bid = (int)blockIdx.x - b0, nbid = g.b_end - b0;
+#define MPWSD_RESOLVE_BODY(NW)                                                                                        resolve_merge_body<FLOAT, NW>(sh, bid, nbid, g.z, g.cw, g.metric, g.moves, g.KP, g.P, g.hdr, t, T, g.keys,                                       g.fid, L, LP, g.out_moves, g.tag, g.fl_in, g.fl_out, g.act_out, g.fcap)
+    switch (g.NW) {  // uniform over the workgroup
+    case 1: MPWSD_RESOLVE_BODY(1); break;
+    case 2: MPWSD_RESOLVE_BODY(2); break;
+    case 4: MPWSD_RESOLVE_BODY(4); break;
+    default: MPWSD_RESOLVE_BODY(8); break;
+    }
+#undef MPWSD_RESOLVE_BODY
 }
 
 // ---------------------------------------------------------------- select
@@ -1540,6 +1604,45 @@ void launch_resolve_merge(const mpwsd_segment& sg, int L, int T, const SegWs& w,
 #undef MPWSD_RESOLVE_MERGE
 }
 
+// The resolves of iteration t of every segment of a multi-code call in one
+// launch (merging on), each segment with the grid its own launch would have.
+template <bool FLOAT>
+void launch_resolve_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w, int t, hipStream_t s)
+{
+    MultiResolve mr{};
+    const int lp = lanes_per_frame(L);
+    const int64_t frames_per_block = 4 * (WAVE / lp);
+    int blocks = 0;
+    for (int i = 0; i < nseg; ++i) {
+        const mpwsd_segment& sg = segs[i];
+        if (sg.F == 0) continue;
+        const int N = 1 << sg.m;
+        SegResolve& g = mr.s[mr.nseg++];
+        g.z = w[i].z;
+        g.cw = (uint32_t*)w[i].cw;
+        g.metric = w[i].metric;
+        g.moves = sg.moves;
+        g.P = sg.P;
+        g.hdr = w[i].hdr;
+        g.keys = (unsigned long long*)w[i].key64;
+        g.fid = w[i].fid;
+        g.out_moves = sg.out_moves;
+        g.tag = w[i].tag;
+        g.fl_in = t == 0 ? nullptr : w[i].fl[t & 1];
+        g.fl_out = w[i].fl[(t + 1) & 1];
+        g.act_out = w[i].act[(t + 1) & 1];
+        g.KP = kpad(N);
+        g.NW = N / 32;
+        g.fcap = (int)sg.F;
+        blocks += (int)std::max<int64_t>(
+            1, std::min<int64_t>((sg.F + frames_per_block - 1) / frames_per_block, 4 * device_cus()));
+        g.b_end = blocks;
+    }
+    if (mr.nseg > 0)
+        hipLaunchKernelGGL(resolve_merge_multi_kernel<FLOAT>, dim3((unsigned)blocks), dim3(256), 0, s, mr, t, T, L,
+                           lp);
+}
+
 void seg_resolve(const mpwsd_segment& sg, int L, int T, const SegWs& w, int t, bool merge, hipStream_t s)
 {
     if (merge) {
@@ -1596,7 +1699,8 @@ int run_segment(const mpwsd_segment& sg, int L, int T, const SegWs& w, int32_t* 
     return MPWSD_OK;
 }
 
-// Several int8 segments: every iteration's search of all codes is ONE launch.
+// Several int8 segments: every iteration's search of all codes is ONE launch,
+// and so is its resolve (with merging).
 int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w, int32_t* stats, hipEvent_t* ev,
               const int* variant, const int* blocks_per_cu, bool merge, hipStream_t s)
 {
@@ -1656,8 +1760,12 @@ int run_multi(const mpwsd_segment* segs, int nseg, int L, int T, const SegWs* w,
                           segs[i].P, w[i].act[t & 1], w[i].hdr + ncol(t), (long long*)w[i].key64, -1, 0, s);
         }
         if (ev) (void)hipEventRecord(ev[2 * t + 1], s);
-        for (int i = 0; i < nseg; ++i)
-            if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, merge, s);
+        if (merge) {
+            launch_resolve_multi<false>(segs, nseg, L, T, w, t, s);  // int8: the only form of a multi-code call
+        } else {
+            for (int i = 0; i < nseg; ++i)
+                if (segs[i].F > 0) seg_resolve(segs[i], L, T, w[i], t, merge, s);
+        }
     }
     for (int i = 0; i < nseg; ++i)
         if (segs[i].F > 0) seg_epilogue(segs[i], L, T, w[i], merge, stats, s);
