@@ -470,7 +470,8 @@ int mpwsd_server_create(const mpwsd_server_code* codes, int ncodes, void* arena,
  * scales (8 / sigma^2), tags[n].  The data is copied; nothing is enqueued.
  * Submission may run on other threads than the one that calls
  * mpwsd_server_tick and mpwsd_server_poll (each call locks the code's
- * queue); tick, poll and destroy stay on one thread. */
+ * queue); tick, poll and destroy stay on one thread, and every submitting
+ * thread must have returned before mpwsd_server_destroy. */
 int mpwsd_server_submit(mpwsd_server* server, int code, int n, const float* y, const float* scale,
                         const uint64_t* tags);
 
