@@ -148,7 +148,7 @@ def cpu_baseline(segs, ys, L, T, nframes, threads, radius=1, osd=None):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus %d requested); "
+        print("bench.py: measures one GPU only (--gpus %d requested); "
               "the decoder shards by frame with no communication between GPUs" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
