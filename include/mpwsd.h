@@ -493,7 +493,8 @@ int mpwsd_server_destroy(mpwsd_server* server);
  * producer thread of its own), the calling thread ticks the server
  * continuously, and the result of frame i is written to out[i] (tag = i),
  * its t_submit being the scheduled arrival (so latencies include any delay
- * in submitting).  pools[c] is a host [rows][N] float array for code c.
+ * in submitting).  pools[c] is a host [rows][N] float array for code c;
+ * arrivals are seconds in [0, 1e9) (MPWSD_ERR_ARG otherwise, nothing run).
  * Returns 0 when every frame completed.
  */
 int mpwsd_serve_trace(mpwsd_server* server, int64_t n, const int32_t* code, const int64_t* row,

@@ -732,7 +732,8 @@ extern "C" int mpwsd_serve_trace(mpwsd_server* s, int64_t n, const int32_t* code
     if (!s || n < 0 || (n > 0 && (!code || !row || !scale || !arrival || !pools || !out)))
         return fail(MPWSD_ERR_ARG, "mpwsd_serve_trace: bad arguments");
     for (int64_t i = 0; i < n; ++i)
-        if (code[i] < 0 || code[i] >= (int)s->codes.size() || !pools[code[i]] || row[i] < 0)
+        if (code[i] < 0 || code[i] >= (int)s->codes.size() || !pools[code[i]] || row[i] < 0 ||
+            !(arrival[i] >= 0.0 && arrival[i] < 1e9))  // also rejects NaN: every arrival must come
             return fail(MPWSD_ERR_ARG, "mpwsd_serve_trace: bad trace entry %lld", (long long)i);
     const double t0 = now_s();
     // a producer thread submits each frame at its arrival time (as requests

@@ -108,3 +108,24 @@ def test_memory_gate_small_capacity(setup):
     srv.close()
     assert (res["tag"] == np.arange(n)).all()
     assert set(np.unique(res["stage"])) <= {1, 2}
+
+
+def test_trace_rejects_bad_arrivals(setup):
+    """A trace whose arrival times cannot all come (NaN, negative) is refused
+    before anything runs; the server stays usable."""
+    say("case: serving trace with bad arrivals")
+    codes, pools, scales, truth = setup
+    specs = [dict(L=L, T=T, capacity=64) for wl, L, T in serve.MIX]
+    srv = serve.Server(codes, specs)
+    n = 9
+    code = np.arange(n, dtype=np.int32) % 3
+    row = np.arange(n, dtype=np.int64)
+    scale = np.array([scales[c][r] for c, r in zip(code, row)], np.float32)
+    for bad in (np.nan, -1.0):
+        arr = np.zeros(n)
+        arr[4] = bad
+        with pytest.raises(Exception, match="bad trace entry 4"):
+            srv.serve_trace(code, row, scale, arr, pools)
+    res = serve.results_table(srv.serve_trace(code, row, scale, np.zeros(n), pools))
+    srv.close()
+    assert (res["tag"] == np.arange(n)).all()
