@@ -120,3 +120,30 @@ def test_merge_edges(name, r, m, F, L, T, dtype):
         assert follows > 0 and stops > 0
     if L == 32:
         assert chains > 0
+
+
+@pytest.mark.parametrize("L", [3, 5, 32])
+def test_multi_code_resolve_odd_lists(L):
+    """One resolve launch for several codes (a multi-code call), with list
+    sizes that leave lanes idle in a frame's group (3, 5) or put two frames on
+    a wave (32): every output and the searched counts equal each code decoded
+    alone."""
+    say("case: multi-code merge, L", L)
+    T = 5
+    parts = [(2, 6, 150), (3, 7, 60), (2, 7, 90)]
+    cases = []
+    for i, (r, m, F) in enumerate(parts):
+        q, y, anchors, supp = make_case(r, m, F, L, 300 + 10 * L + i)
+        cases.append((code(r, m), q, anchors))
+    st = D.Stage2([(cd, q.shape[0]) for cd, q, a in cases], L, T, "i8", DEV)
+    ancs = [torch.from_numpy(np.packbits(a, axis=-1, bitorder="little")).to(DEV) for cd, q, a in cases]
+    outs = st.run([torch.from_numpy(q).to(DEV) for cd, q, a in cases], ancs, [None] * len(cases))
+    torch.cuda.synchronize()
+    outs = [{k: v.cpu().numpy() for k, v in o.items()} for o in outs]
+    tot = np.zeros(2 + T, np.int64)
+    for (cd, q, anchors), o in zip(cases, outs):
+        ref, stats = run(cd, q, anchors, L, T, "i8", True)
+        tot += stats
+        for k in ref:
+            assert np.array_equal(o[k], ref[k]), k
+    assert np.array_equal(st.stats.cpu().numpy(), tot)
