@@ -129,3 +129,42 @@ def test_trace_rejects_bad_arrivals(setup):
     res = serve.results_table(srv.serve_trace(code, row, scale, np.zeros(n), pools))
     srv.close()
     assert (res["tag"] == np.arange(n)).all()
+
+
+def test_submit_from_other_threads(setup):
+    """Two threads submit frames while this thread ticks and polls (the
+    header lets submission run on other threads): every frame comes back
+    once, and equal to mpwsd_decode_batch's result for it."""
+    import threading
+    import time
+    say("case: serving with two submitting threads")
+    codes, pools, scales, truth = setup
+    refs = batch_reference(codes, pools, scales)
+    specs = [dict(L=L, T=T, capacity=64) for wl, L, T in serve.MIX]
+    srv = serve.Server(codes, specs)
+    jobs = [[(c, r) for c in range(3) for r in range(ROWS) if (c + r) % 2 == t] for t in range(2)]
+
+    def producer(t):
+        for c, r in jobs[t]:
+            srv.submit(c, pools[c][r:r + 1], scales[c][r:r + 1], np.array([c * ROWS + r], np.uint64))
+
+    threads = [threading.Thread(target=producer, args=(t,)) for t in range(2)]
+    for th in threads:
+        th.start()
+    got = []
+    deadline = time.time() + 120
+    while len(got) < 3 * ROWS and time.time() < deadline:
+        srv.tick()
+        got += srv.poll()
+    for th in threads:
+        th.join()
+    srv.close()
+    res = serve.results_table((serve.Result * len(got))(*got))
+    assert np.array_equal(np.sort(res["tag"]), np.arange(3 * ROWS))
+    N = [1 << wl.m for wl, L, T in serve.MIX]
+    for i in range(len(res)):
+        c, r = divmod(int(res["tag"][i]), ROWS)
+        ref = refs[c]
+        assert res["stage"][i] == ref["stage"][r] and res["k"][i] == ref["k"][r], (c, r)
+        assert res["metric"][i] == ref["metric"][r], (c, r)
+        assert np.array_equal(res["cw"][i][:N[c] // 8], ref["cw"][r]), (c, r)
